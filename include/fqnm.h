@@ -1,0 +1,271 @@
+/*
+ * fqnm.h -- C ABI of the MI355X (gfx950) implementation of the Fast Quantised
+ * Numerical Method (FQNM), arXiv 2604.06947.
+ *
+ * The method evolves integer states q_i instead of floating-point fields
+ * (Sec. 2, eq:quantisation).  Every interface i+1/2 carries an integer count
+ * flux F_{i+1/2} = T(q_i, q_{i+1}) built from rounded transfer maps
+ * (eq:flux_table, eq:numerical_count_flux_definition), and every cell applies
+ *     q_i <- q_i - (F_{i+1/2} - F_{i-1/2})         (eq:update_rule_conservative_form)
+ * so the total count is conserved exactly by integer telescoping
+ * (Sec. 2.3, eq:exact_conservation).  Fields are observables u_i = delta*q_i
+ * (eq:reconstruction_operator).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns fqnm_status: 0 on success, a negative code on
+ *     failure.  fqnm_last_error() returns a thread-local message describing the
+ *     last failure of the calling thread.  No C++ exception crosses this ABI.
+ *   - Host pointers are read (or written) during the call only; the caller
+ *     keeps ownership.  Device memory allocated by the library belongs to the
+ *     object that allocated it and is freed by its destroy call.  A device
+ *     pointer passed to fqnm_create_on_device is borrowed and must outlive the
+ *     context.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; calls that return host data synchronise it.
+ *   - An object is not thread-safe; distinct objects on distinct streams are
+ *     independent.  After a HIP runtime error an object is poisoned and every
+ *     later call on it returns FQNM_ERR_DEVICE.
+ *   - Cells are indexed 0..n-1 with centres x_i = i*dx (Sec. 2).  A scalar
+ *     state is n integers; an Euler state is three arrays of n integers
+ *     (rho, m, E) stored one after the other (structure of arrays).
+ *   - "round" is IEEE round-half-to-even; every floating-point operation of a
+ *     transfer map is one IEEE operation in a fixed order with no contraction,
+ *     so the integer trajectory is a deterministic function of the inputs.
+ */
+#ifndef FQNM_H
+#define FQNM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FQNM_ABI_VERSION 1u
+
+typedef enum {
+  FQNM_OK = 0,
+  FQNM_ERR_ARG = -1,         /* invalid argument (null pointer, bad enum, non-positive constant) */
+  FQNM_ERR_CFL = -2,         /* CFL number nu = dt/dx * max|f'| exceeds 1 (Sec. 2.2, eq:cfl_number) */
+  FQNM_ERR_RANGE = -3,       /* integer or FP64-exactness range would be exceeded                */
+  FQNM_ERR_OOM = -4,         /* device allocation failed, or a server budget cannot hold a request */
+  FQNM_ERR_DEVICE = -5,      /* HIP runtime error (sticky for the object)                         */
+  FQNM_ERR_STATE = -6,       /* call not valid in the object's current state                      */
+  FQNM_ERR_BUSY = -7,        /* resource temporarily unavailable (server queue full)              */
+  FQNM_ERR_UNSUPPORTED = -8  /* valid request that this build does not implement                  */
+} fqnm_status;
+
+/* Flux kinds.  Split kinds round f+ and f- separately (eq:flux_table); two-point
+ * kinds round the interface flux once
+ * (Sec. 2.2, eq:transfer_operator_equivalence_definition). */
+typedef enum {
+  FQNM_FLUX_UPWIND = 0,          /* f = a u; f+ = max(a,0)u, f- = min(a,0)u; phi = rint((a*lambda)*q) */
+  FQNM_FLUX_BURGERS_EO = 1,      /* f = u^2/2, Engquist-Osher split f+ = max(u,0)^2/2, f- = min(u,0)^2/2;
+                                    phi = rint(((delta*lambda)*0.5) * s^2)                        */
+  FQNM_FLUX_BURGERS_GODUNOV = 2, /* f = u^2/2, two-point Godunov flux, one rounding              */
+  FQNM_FLUX_LF_LINEAR = 3,       /* f = a u, Lax-Friedrichs split (f +- alpha u)/2 (Sec. 2,
+                                    eq:flux_splitting)                                           */
+  FQNM_FLUX_LF_BURGERS = 4,      /* f = u^2/2, Lax-Friedrichs split                              */
+  FQNM_FLUX_EULER_ROE = 5,       /* Euler equations, 3 components, Roe flux in FP64 then
+                                    T_c = rint((F_c*lambda)/delta) per component (Sec. 3.3)      */
+  FQNM_FLUX_EULER_ROE_EF = 6,    /* as above with an entropy fix of the acoustic waves            */
+  FQNM_FLUX_BURGERS_MURMAN_ROE = 7 /* f = u^2/2, two-point Murman-Roe flux, one rounding         */
+} fqnm_flux;
+
+typedef enum { FQNM_BC_PERIODIC = 0, FQNM_BC_OUTFLOW = 1 } fqnm_bc;
+typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
+
+/* How a split transfer map is evaluated on the device.  Tabulation is an
+ * execution strategy, not the method (Sec. 2, after eq:flux_table): both
+ * modes produce the same integers.  LUT mode tabulates phi+ and phi- over the
+ * initial state range [min q0, max q0], which bounds every later state by the
+ * discrete maximum principle (Lemma cfl_monotone (i)); it is accepted for the
+ * kinds for which that principle holds (UPWIND, BURGERS_EO). */
+typedef enum { FQNM_EVAL_AUTO = 0, FQNM_EVAL_DIRECT = 1, FQNM_EVAL_LUT = 2 } fqnm_eval;
+
+/* Problem statement (Sec. 2): flux kind and its constants, resolution delta,
+ * cell width dx, lambda = dt/dx, boundary kind, storage width, cell count. */
+typedef struct {
+  uint32_t abi_version; /* must equal FQNM_ABI_VERSION                                  */
+  int32_t flux;         /* fqnm_flux                                                    */
+  int32_t bc;           /* fqnm_bc                                                      */
+  int32_t itype;        /* fqnm_itype; Euler kinds require FQNM_I64                     */
+  int32_t eval;         /* fqnm_eval (scalar split kinds only; others ignore it)        */
+  int32_t reserved;     /* must be 0                                                    */
+  double a;             /* advection speed (UPWIND, LF_LINEAR)                          */
+  double alpha;         /* LF dissipation speed, alpha >= max|f'| on the state range    */
+  double gamma;         /* ratio of specific heats (Euler kinds), > 1                   */
+  double delta;         /* quantisation resolution, > 0                                */
+  double dx;            /* cell width, > 0 (informational: the update uses lambda)      */
+  double lambda;        /* dt/dx, > 0                                                   */
+  int64_t n;            /* cells, >= 1; components = 3 for Euler kinds, else 1          */
+} fqnm_problem;
+
+/* Exact diagnostics of a state (Sec. 2.2 Lemma cfl_monotone, Sec. 2.3).  Sums
+ * and total variations are 128-bit two's-complement values split into a
+ * signed high and an unsigned low word.  Unused components are zero. */
+typedef struct {
+  int32_t components;
+  int32_t reserved;
+  int64_t steps_done;   /* steps applied since create                                    */
+  int64_t sum_hi[3];    /* sum_i q_i per component                                       */
+  uint64_t sum_lo[3];
+  int64_t qmin[3];
+  int64_t qmax[3];
+  int64_t tv_hi[3];     /* sum_i |q_{i+1} - q_i| (periodic: including the wrap term)     */
+  uint64_t tv_lo[3];
+  int64_t ledger[3];    /* outflow: sum over steps of F_{-1/2} - F_{n-1/2}, the net count
+                           that entered through the boundaries; periodic: 0.  Invariant:
+                           sum(q) - sum(q0) == ledger                                    */
+} fqnm_invariants;
+
+/* Launch plan of the single-grid stepper.  kernel 0 = one step per pass
+ * ("stream"), 1 = temporal blocking: every wavefront keeps a tile of
+ * 64*vec cells in registers and advances it `depth` steps per pass over
+ * memory.  Zero fields mean "choose". */
+typedef struct {
+  int32_t kernel;
+  int32_t vec;          /* cells per lane                                                */
+  int32_t depth;        /* steps per pass (kernel 1)                                     */
+  int32_t eval;         /* resolved fqnm_eval (read-only in fqnm_get_plan)               */
+} fqnm_plan;
+
+typedef struct fqnm_ctx fqnm_ctx;
+
+const char* fqnm_last_error(void);
+const char* fqnm_version(void);
+
+/* Create a solver from an integer initial state q0_host (n or 3n integers of
+ * the problem's itype).  Validates the problem: positive finite delta, dx,
+ * lambda (FQNM_ERR_ARG); the CFL number over [min q0, max q0] for scalar
+ * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^52 so that q converts
+ * to FP64 exactly, q^2 < 2^53 for Burgers kinds, and for I32 that
+ * |q| + 2 max|F| < 2^31 on that range (FQNM_ERR_RANGE).  Copies q0 to the
+ * device on hip_stream and builds the LUT when the eval mode asks for it. */
+fqnm_status fqnm_create(const fqnm_problem* prob, const void* q0_host, void* hip_stream,
+                        fqnm_ctx** out);
+
+/* As fqnm_create, from a real initial field u0_host (n or 3n doubles): the
+ * device quantises q0_i = rint(u0_i / delta) (Sec. 2, eq:quantisation). */
+fqnm_status fqnm_create_from_field(const fqnm_problem* prob, const double* u0_host,
+                                   void* hip_stream, fqnm_ctx** out);
+
+/* As fqnm_create, with the initial state already on the device in d_q
+ * (components*n integers of the problem's itype, borrowed).  After every
+ * fqnm_step the current state is again in d_q. */
+fqnm_status fqnm_create_on_device(const fqnm_problem* prob, void* d_q, void* hip_stream,
+                                  fqnm_ctx** out);
+
+/* Advance n_steps >= 0 time steps of eq:update_rule_conservative_form.
+ * Asynchronous: enqueued on the context's stream. */
+fqnm_status fqnm_step(fqnm_ctx* ctx, int64_t n_steps);
+
+/* Copy the current integer state to the host (components*n integers). Syncs. */
+fqnm_status fqnm_get_state(fqnm_ctx* ctx, void* q_host);
+
+/* Device address of the current state (valid until the next fqnm_step). */
+fqnm_status fqnm_state_device(fqnm_ctx* ctx, void** d_q);
+
+/* Reconstruct u_i = delta*q_i (eq:reconstruction_operator) into u_host
+ * (components*n doubles).  Syncs. */
+fqnm_status fqnm_reconstruct(fqnm_ctx* ctx, double* u_host);
+
+/* As fqnm_reconstruct into device memory d_u; asynchronous. */
+fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u);
+
+/* Exact sums, extrema, total variation and boundary ledger.  Syncs. */
+fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out);
+
+fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out);
+/* Force a plan (zero fields keep the current choice).  FQNM_ERR_ARG if the
+ * combination is not available for this problem. */
+fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan);
+/* Time the candidate plans on a scratch copy of the state (the state itself is
+ * not advanced), keep the fastest, and remember it for problems of the same
+ * shape in this process and in the file named by FQNM_AUTOTUNE_CACHE, if set. */
+fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial);
+
+fqnm_status fqnm_destroy(fqnm_ctx* ctx); /* NULL-safe */
+
+/* Self-check of the FP64 operations the Euler transfer relies on: evaluates,
+ * with the library's own device code generation, out_sqrt[i] = sqrt(d_a[i])
+ * and out_div[i] = d_a[i] / d_b[i] for i < n (all device pointers), so that a
+ * caller can compare them with a correctly rounded host reference.  Syncs. */
+fqnm_status fqnm_fp64_selfcheck(const double* d_a, const double* d_b, double* d_out_sqrt,
+                                double* d_out_div, int64_t n, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batching: many independent instances (each its own problem, state and step
+ * count) advanced together.  Instances that fit one workgroup run every one
+ * of their steps inside one persistent launch with their state held in
+ * registers; larger ones use the single-grid stepper.  The whole run is
+ * captured once as a HIP graph and replayed.
+ * ---------------------------------------------------------------------- */
+typedef struct fqnm_batch fqnm_batch;
+
+/* probs[k], q0s[k] (host, the instance's itype) and steps[k] >= 0 describe
+ * instance k.  Scalar kinds only. */
+fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
+                              const int64_t* steps, int32_t count, void* hip_stream,
+                              fqnm_batch** out);
+/* Restore every instance to its initial state (for repeated runs). Async. */
+fqnm_status fqnm_batch_reset(fqnm_batch* b);
+/* Advance every instance by its own step count in one batched run. Async. */
+fqnm_status fqnm_batch_run(fqnm_batch* b);
+/* The comparison loop: the same work as one single-grid run per instance,
+ * issued one instance after another on the stream. Async. */
+fqnm_status fqnm_batch_run_per_instance(fqnm_batch* b);
+fqnm_status fqnm_batch_get_state(fqnm_batch* b, int32_t idx, void* q_host); /* syncs */
+fqnm_status fqnm_batch_destroy(fqnm_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests.  A worker thread admits
+ * queued requests while their device footprint fits the budget, keeps their
+ * integer state resident, and advances every admitted request by up to
+ * tick_steps steps per tick in one batched launch sequence.  Requests that
+ * arrive while a tick runs join at the next tick.  Each request's trajectory
+ * is the same integers it would have alone.
+ * ---------------------------------------------------------------------- */
+typedef struct fqnm_server fqnm_server;
+
+typedef struct {
+  uint64_t id;
+  int32_t status;       /* fqnm_status of the request                                    */
+  int32_t components;
+  int64_t n;
+  int64_t steps;
+  double t_submit;      /* seconds on the library's monotonic clock                      */
+  double t_admit;
+  double t_done;
+} fqnm_completion;
+
+typedef struct {
+  int64_t submitted, admitted, completed, queued, active;
+  int64_t ticks;
+  int64_t bytes_in_use;
+  int64_t peak_bytes;
+  double cell_updates;  /* total cells*steps*components... counted per cell-update       */
+} fqnm_server_stats;
+
+fqnm_status fqnm_server_create(size_t device_budget_bytes, int32_t tick_steps, void* hip_stream,
+                               fqnm_server** out);
+/* Queue a request.  q0_host is copied during the call; the final state is
+ * written to out_host (same size) before the request is reported complete;
+ * out_host must stay valid until then.  FQNM_ERR_OOM if the request alone
+ * exceeds the budget. */
+fqnm_status fqnm_server_submit(fqnm_server* s, const fqnm_problem* prob, const void* q0_host,
+                               int64_t n_steps, void* out_host, uint64_t* req_id);
+/* Move up to max completions into out; *n_out receives the count.  Never blocks. */
+fqnm_status fqnm_server_poll(fqnm_server* s, fqnm_completion* out, int32_t max, int32_t* n_out);
+/* Block until every submitted request has completed or timeout_s elapsed
+ * (FQNM_ERR_BUSY on timeout). */
+fqnm_status fqnm_server_drain(fqnm_server* s, double timeout_s);
+fqnm_status fqnm_server_stats_get(fqnm_server* s, fqnm_server_stats* out);
+double fqnm_server_now(void); /* the clock of fqnm_completion, in seconds */
+fqnm_status fqnm_server_destroy(fqnm_server* s); /* cancels queued work; NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FQNM_H */

@@ -1,0 +1,638 @@
+// api.hip -- host runtime behind the C ABI of include/fqnm.h: validation,
+// device memory, quantisation, LUT construction, the step loop, diagnostics,
+// launch plans and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fqnm_internal.h"
+#include "runtime.h"
+
+namespace fqnm {
+
+static thread_local std::string tl_error;
+void set_error(const std::string& msg) { tl_error = msg; }
+
+fqnm_status fail(fqnm_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+fqnm_status hip_fail(hipError_t e, const char* what) {
+  return fail(FQNM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_euler(int flux) { return flux == FQNM_FLUX_EULER_ROE || flux == FQNM_FLUX_EULER_ROE_EF; }
+bool is_burgers(int flux) {
+  return flux == FQNM_FLUX_BURGERS_EO || flux == FQNM_FLUX_BURGERS_GODUNOV ||
+         flux == FQNM_FLUX_BURGERS_MURMAN_ROE || flux == FQNM_FLUX_LF_BURGERS;
+}
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+fqnm_status validate_problem(const fqnm_problem* p) {
+  if (!p) return fail(FQNM_ERR_ARG, "problem is NULL");
+  if (p->abi_version != FQNM_ABI_VERSION) return fail(FQNM_ERR_ARG, "abi_version mismatch");
+  if (p->flux < 0 || p->flux > FQNM_FLUX_BURGERS_MURMAN_ROE)
+    return fail(FQNM_ERR_ARG, "unknown flux kind");
+  if (p->bc != FQNM_BC_PERIODIC && p->bc != FQNM_BC_OUTFLOW)
+    return fail(FQNM_ERR_ARG, "unknown boundary kind");
+  if (p->itype != FQNM_I32 && p->itype != FQNM_I64) return fail(FQNM_ERR_ARG, "unknown itype");
+  if (p->eval < FQNM_EVAL_AUTO || p->eval > FQNM_EVAL_LUT)
+    return fail(FQNM_ERR_ARG, "unknown eval mode");
+  if (p->reserved != 0) return fail(FQNM_ERR_ARG, "reserved field must be 0");
+  if (!finite_pos(p->delta) || !finite_pos(p->dx) || !finite_pos(p->lambda))
+    return fail(FQNM_ERR_ARG, "delta, dx and lambda must be positive and finite");
+  if (p->n < 1 || p->n > (int64_t(1) << 36)) return fail(FQNM_ERR_ARG, "n out of range");
+  if (!std::isfinite(p->a)) return fail(FQNM_ERR_ARG, "a must be finite");
+  if ((p->flux == FQNM_FLUX_LF_LINEAR || p->flux == FQNM_FLUX_LF_BURGERS) && !finite_pos(p->alpha))
+    return fail(FQNM_ERR_ARG, "alpha must be positive for Lax-Friedrichs kinds");
+  if (is_euler(p->flux)) {
+    if (p->itype != FQNM_I64) return fail(FQNM_ERR_ARG, "Euler kinds need FQNM_I64 states");
+    if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) return fail(FQNM_ERR_ARG, "gamma must be > 1");
+    if (p->eval == FQNM_EVAL_LUT) return fail(FQNM_ERR_ARG, "Euler kinds have no LUT mode");
+  }
+  if (p->eval == FQNM_EVAL_LUT && p->flux != FQNM_FLUX_UPWIND && p->flux != FQNM_FLUX_BURGERS_EO)
+    return fail(FQNM_ERR_ARG, "LUT mode is available for UPWIND and BURGERS_EO only");
+  return FQNM_OK;
+}
+
+int policy_of(const fqnm_problem& p, bool lut) {
+  if (lut) return P_LUT;
+  switch (p.flux) {
+    case FQNM_FLUX_UPWIND: return p.a >= 0.0 ? P_UPWIND_POS : P_UPWIND_NEG;
+    case FQNM_FLUX_BURGERS_EO: return P_EO;
+    case FQNM_FLUX_BURGERS_GODUNOV: return P_GODUNOV;
+    case FQNM_FLUX_LF_LINEAR: return P_LF_LINEAR;
+    case FQNM_FLUX_LF_BURGERS: return P_LF_BURGERS;
+    case FQNM_FLUX_BURGERS_MURMAN_ROE: return P_MURMAN_ROE;
+    default: return -1;
+  }
+}
+
+int direct_split_policy(const fqnm_problem& p) {
+  return p.flux == FQNM_FLUX_UPWIND ? (p.a >= 0.0 ? P_UPWIND_POS : P_UPWIND_NEG) : P_EO;
+}
+
+XParams xparams_of(const fqnm_problem& p) {
+  XParams x;
+  std::memset(&x, 0, sizeof x);
+  x.c = p.a * p.lambda;
+  x.h = (p.delta * p.lambda) * 0.5;
+  x.a = p.a;
+  x.alpha = p.alpha;
+  x.delta = p.delta;
+  x.lambda = p.lambda;
+  return x;
+}
+
+// Host bound of |phi+-| on [lo, hi] for the range checks (the maps are monotone,
+// so the extremes are at the end points; +1 covers rounding).
+static double map_bound(const fqnm_problem& p, int64_t lo, int64_t hi) {
+  const double qa = std::max(std::fabs((double)lo), std::fabs((double)hi));
+  const double lam = p.lambda, d = p.delta;
+  switch (p.flux) {
+    case FQNM_FLUX_UPWIND: return std::fabs(p.a * lam) * qa + 1.0;
+    case FQNM_FLUX_BURGERS_EO:
+    case FQNM_FLUX_BURGERS_GODUNOV:
+    case FQNM_FLUX_BURGERS_MURMAN_ROE: return 2.0 * ((d * lam) * 0.5 * qa * qa + 1.0);
+    case FQNM_FLUX_LF_LINEAR: return 2.0 * ((std::fabs(p.a) + p.alpha) * 0.5 * lam * qa + 1.0);
+    case FQNM_FLUX_LF_BURGERS:
+      return 2.0 * ((0.5 * d * qa * qa + p.alpha * qa) * 0.5 * lam + 1.0);
+    default: return 0.0;
+  }
+}
+
+fqnm_status validate_range(const fqnm_problem& p, int64_t lo, int64_t hi) {
+  const double qa = std::max(std::fabs((double)lo), std::fabs((double)hi));
+  if (qa >= 4503599627370496.0) return fail(FQNM_ERR_RANGE, "|q| must stay below 2^52");
+  if (is_euler(p.flux)) return FQNM_OK;
+  if (is_burgers(p.flux) && qa > 94906265.0)
+    return fail(FQNM_ERR_RANGE, "Burgers kinds need q^2 < 2^53 (|q| <= 94906265)");
+  // CFL (Sec. 2.2, eq:cfl_number): nu = dt/dx * max|f'| <= 1 on the state range.
+  double nu = 0.0;
+  switch (p.flux) {
+    case FQNM_FLUX_UPWIND: nu = std::fabs(p.a) * p.lambda; break;
+    case FQNM_FLUX_BURGERS_EO:
+    case FQNM_FLUX_BURGERS_GODUNOV:
+    case FQNM_FLUX_BURGERS_MURMAN_ROE: nu = p.lambda * (p.delta * qa); break;
+    case FQNM_FLUX_LF_LINEAR:
+      if (p.alpha < std::fabs(p.a)) return fail(FQNM_ERR_CFL, "LF needs alpha >= |a|");
+      nu = p.alpha * p.lambda;
+      break;
+    case FQNM_FLUX_LF_BURGERS:
+      if (p.alpha < p.delta * qa) return fail(FQNM_ERR_CFL, "LF needs alpha >= max|u|");
+      nu = p.alpha * p.lambda;
+      break;
+  }
+  if (nu > 1.0) {
+    char b[128];
+    std::snprintf(b, sizeof b, "CFL number %.6g exceeds 1", nu);
+    return fail(FQNM_ERR_CFL, b);
+  }
+  const double lim = p.itype == FQNM_I32 ? 2147483647.0 : 4611686018427387904.0;
+  if (qa + 2.0 * map_bound(p, lo, hi) >= lim)
+    return fail(FQNM_ERR_RANGE, "states or transfers would overflow the storage type");
+  return FQNM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans and the in-process autotune cache.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::string, fqnm_plan> g_tune;
+
+std::string plan_key(const fqnm_problem& p, int pol) {
+  char b[160];
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= p.n) ++lg;
+  std::snprintf(b, sizeof b, "i%d_p%d_b%d_n2^%d", p.itype, pol, p.bc, lg);
+  return b;
+}
+
+static void load_tune_file() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* f = std::getenv("FQNM_AUTOTUNE_CACHE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "r");
+  if (!fp) return;
+  char key[160];
+  fqnm_plan pl;
+  while (std::fscanf(fp, "%159s %d %d %d %d", key, &pl.kernel, &pl.vec, &pl.depth, &pl.eval) == 5)
+    g_tune[key] = pl;
+  std::fclose(fp);
+}
+
+static void save_tune_file() {
+  const char* f = std::getenv("FQNM_AUTOTUNE_CACHE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "w");
+  if (!fp) return;
+  for (auto& kv : g_tune)
+    std::fprintf(fp, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.kernel, kv.second.vec,
+                 kv.second.depth, kv.second.eval);
+  std::fclose(fp);
+}
+
+bool lookup_plan(const std::string& key, fqnm_plan* out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void store_plan(const std::string& key, const fqnm_plan& pl) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file();
+  g_tune[key] = pl;
+  save_tune_file();
+}
+
+fqnm_plan default_plan(const fqnm_problem& p) {
+  fqnm_plan pl;
+  pl.kernel = K_TBLOCK;
+  pl.vec = p.itype == FQNM_I32 ? 16 : 8;
+  pl.depth = p.itype == FQNM_I32 ? 32 : 16;
+  pl.eval = 0;
+  return pl;
+}
+
+}  // namespace fqnm
+
+using namespace fqnm;
+
+// ---------------------------------------------------------------------------
+// Context.
+// ---------------------------------------------------------------------------
+#define CTX_HIP(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) {                        \
+      ctx->poisoned = true;                        \
+      return hip_fail(e_, what);                   \
+    }                                              \
+  } while (0)
+
+static fqnm_status ctx_alloc(fqnm_ctx* ctx, void* borrowed) {
+  const size_t bytes = ctx->state_bytes();
+  if (borrowed) {
+    if ((reinterpret_cast<uintptr_t>(borrowed) & 15) != 0)
+      return fail(FQNM_ERR_ARG, "device state must be 16-byte aligned");
+    ctx->buf[0] = borrowed;
+    ctx->borrowed = true;
+  } else if (hipMalloc(&ctx->buf[0], bytes) != hipSuccess) {
+    return fail(FQNM_ERR_OOM, "hipMalloc of the state failed");
+  }
+  if (hipMalloc(&ctx->buf[1], bytes) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "hipMalloc of the second state buffer failed");
+  if (hipMalloc(&ctx->d_ledger, 3 * sizeof(long long)) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "hipMalloc of the ledger failed");
+  CTX_HIP(hipMemsetAsync(ctx->d_ledger, 0, 3 * sizeof(long long), ctx->stream), "ledger reset");
+  return FQNM_OK;
+}
+
+static void ctx_free(fqnm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream_sync_on_free) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->buf[0] && !ctx->borrowed) (void)hipFree(ctx->buf[0]);
+  if (ctx->buf[1]) (void)hipFree(ctx->buf[1]);
+  if (ctx->d_ledger) (void)hipFree(ctx->d_ledger);
+  if (ctx->d_lut) (void)hipFree(ctx->d_lut);
+  if (ctx->d_u) (void)hipFree(ctx->d_u);
+  if (ctx->d_red) (void)hipFree(ctx->d_red);
+  if (ctx->d_err) (void)hipFree(ctx->d_err);
+  delete ctx;
+}
+
+// Range of component 0 of the current state via the device reduction.
+static fqnm_status device_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi) {
+  const int64_t nb = reduce_blocks(ctx->prob.n);
+  if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
+  const char* q = static_cast<const char*>(ctx->buf[ctx->cur]) +
+                  comp * ctx->prob.n * ctx->esize;
+  CTX_HIP(launch_reduce(ctx->prob.itype, q, ctx->prob.n, 0, ctx->d_red, ctx->stream), "reduce");
+  std::vector<ReducePartial> h(nb);
+  CTX_HIP(hipMemcpyAsync(h.data(), ctx->d_red, sizeof(ReducePartial) * nb, hipMemcpyDeviceToHost,
+                         ctx->stream), "copy partials");
+  CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+  int64_t a = INT64_MAX, b = INT64_MIN;
+  for (auto& r : h) {
+    a = std::min(a, r.qmin);
+    b = std::max(b, r.qmax);
+  }
+  *lo = a;
+  *hi = b;
+  return FQNM_OK;
+}
+
+// Shared tail of the create calls: state is on the device in buf[0].
+static fqnm_status ctx_finish(fqnm_ctx* ctx) {
+  const fqnm_problem& p = ctx->prob;
+  if (ctx->euler) {
+    for (int c = 0; c < 3; ++c) {
+      int64_t lo, hi;
+      fqnm_status st = device_minmax(ctx, c, &lo, &hi);
+      if (st) return st;
+      st = validate_range(p, lo, hi);
+      if (st) return st;
+      if (c == 0 && lo <= 0) return fail(FQNM_ERR_RANGE, "density counts must be positive");
+    }
+    ctx->eparams.delta = p.delta;
+    ctx->eparams.lambda = p.lambda;
+    ctx->eparams.g1 = p.gamma - 1.0;
+    ctx->eparams.fix = p.flux == FQNM_FLUX_EULER_ROE_EF;
+    return FQNM_OK;
+  }
+  int64_t lo, hi;
+  fqnm_status st = device_minmax(ctx, 0, &lo, &hi);
+  if (st) return st;
+  st = validate_range(p, lo, hi);
+  if (st) return st;
+  ctx->q0min = lo;
+  ctx->q0max = hi;
+  ctx->xp = xparams_of(p);
+  const bool lut = p.eval == FQNM_EVAL_LUT;
+  if (lut) {
+    const int64_t count = hi - lo + 1;
+    if (count > (int64_t(1) << 28)) return fail(FQNM_ERR_RANGE, "LUT range too large");
+    const size_t eb = p.itype == FQNM_I32 ? 8 : 16;
+    if (hipMalloc(&ctx->d_lut, eb * count) != hipSuccess)
+      return fail(FQNM_ERR_OOM, "hipMalloc of the LUT failed");
+    CTX_HIP(launch_lut_build(p.itype, direct_split_policy(p), ctx->xp, ctx->d_lut, lo, count,
+                             ctx->stream), "LUT build");
+    ctx->xp.lut = ctx->d_lut;
+    ctx->xp.lut_lo = lo;
+    ctx->xp.lut_last = count - 1;
+  }
+  ctx->pol = policy_of(p, lut);
+  ctx->direct_pol = policy_of(p, false);
+  fqnm_plan pl;
+  if (!lookup_plan(plan_key(p, ctx->pol), &pl)) pl = default_plan(p);
+  ctx->plan = pl;
+  ctx->plan.eval = lut ? FQNM_EVAL_LUT : FQNM_EVAL_DIRECT;
+  return FQNM_OK;
+}
+
+static fqnm_status ctx_new(const fqnm_problem* prob, void* stream, fqnm_ctx** out,
+                           fqnm_ctx** made) {
+  if (!out) return fail(FQNM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  fqnm_status st = validate_problem(prob);
+  if (st) return st;
+  fqnm_ctx* ctx = new fqnm_ctx();
+  ctx->prob = *prob;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->euler = is_euler(prob->flux);
+  ctx->comp = ctx->euler ? 3 : 1;
+  ctx->esize = prob->itype == FQNM_I32 ? 4 : 8;
+  *made = ctx;
+  return FQNM_OK;
+}
+
+extern "C" {
+
+const char* fqnm_last_error(void) { return tl_error.c_str(); }
+const char* fqnm_version(void) { return "fqnm-mi355x 1.0 (gfx950, ABI 1)"; }
+
+fqnm_status fqnm_create(const fqnm_problem* prob, const void* q0_host, void* hip_stream,
+                        fqnm_ctx** out) {
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(prob, hip_stream, out, &ctx);
+  if (st) return st;
+  if (!q0_host) { ctx_free(ctx); return fail(FQNM_ERR_ARG, "q0_host is NULL"); }
+  st = ctx_alloc(ctx, nullptr);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(ctx->buf[0], q0_host, ctx->state_bytes(),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) st = hip_fail(e, "copy q0");
+  }
+  if (!st) st = ctx_finish(ctx);
+  if (st) { ctx_free(ctx); return st; }
+  *out = ctx;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_create_from_field(const fqnm_problem* prob, const double* u0_host,
+                                   void* hip_stream, fqnm_ctx** out) {
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(prob, hip_stream, out, &ctx);
+  if (st) return st;
+  if (!u0_host) { ctx_free(ctx); return fail(FQNM_ERR_ARG, "u0_host is NULL"); }
+  st = ctx_alloc(ctx, nullptr);
+  const int64_t total = ctx->comp * prob->n;
+  if (!st && hipMalloc(&ctx->d_u, sizeof(double) * total) != hipSuccess)
+    st = fail(FQNM_ERR_OOM, "hipMalloc of the field failed");
+  if (!st && hipMalloc(&ctx->d_err, sizeof(int)) != hipSuccess)
+    st = fail(FQNM_ERR_OOM, "hipMalloc failed");
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(ctx->d_u, u0_host, sizeof(double) * total,
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream);
+    if (e == hipSuccess)
+      e = launch_quantise(prob->itype, ctx->d_u, ctx->buf[0], total, prob->delta, ctx->d_err,
+                          ctx->stream);
+    int herr = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) st = hip_fail(e, "quantise");
+    else if (herr) st = fail(FQNM_ERR_RANGE, "u0/delta exceeds the storage range");
+  }
+  if (!st) st = ctx_finish(ctx);
+  if (st) { ctx_free(ctx); return st; }
+  *out = ctx;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_create_on_device(const fqnm_problem* prob, void* d_q, void* hip_stream,
+                                  fqnm_ctx** out) {
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(prob, hip_stream, out, &ctx);
+  if (st) return st;
+  if (!d_q) { ctx_free(ctx); return fail(FQNM_ERR_ARG, "d_q is NULL"); }
+  st = ctx_alloc(ctx, d_q);
+  if (!st) st = ctx_finish(ctx);
+  if (st) { ctx_free(ctx); return st; }
+  *out = ctx;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_destroy(fqnm_ctx* ctx) {
+  if (!ctx) return FQNM_OK;
+  ctx->stream_sync_on_free = true;
+  ctx_free(ctx);
+  return FQNM_OK;
+}
+
+}  // extern "C"
+
+// Enqueue n_steps on the context's stream with its current plan.
+fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2], int* cur,
+                              const fqnm_plan& pl) {
+  const fqnm_problem& p = ctx->prob;
+  int64_t left = n_steps;
+  while (left > 0) {
+    const void* src = buf[*cur];
+    void* dst = buf[1 - *cur];
+    int64_t k = 1;
+    hipError_t e;
+    if (ctx->euler) {
+      e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
+                            p.bc, ctx->eparams, ctx->d_ledger, ctx->stream);
+    } else if (pl.kernel == K_STREAM) {
+      e = launch_scalar(p.itype, ctx->pol, K_STREAM, pl.vec, src, dst, p.n, p.bc, 1, 0, ctx->xp,
+                        ctx->d_ledger, ctx->stream);
+    } else {
+      k = std::min<int64_t>(pl.depth, left);
+      const int khalo = scalar_halo(pl.vec, static_cast<int>(k));
+      e = launch_scalar(p.itype, ctx->pol, K_TBLOCK, pl.vec, src, dst, p.n, p.bc,
+                        static_cast<int>(k), khalo, ctx->xp, ctx->d_ledger, ctx->stream);
+    }
+    if (e != hipSuccess) {
+      ctx->poisoned = true;
+      return hip_fail(e, "step launch");
+    }
+    *cur = 1 - *cur;
+    left -= k;
+  }
+  return FQNM_OK;
+}
+
+extern "C" {
+
+fqnm_status fqnm_step(fqnm_ctx* ctx, int64_t n_steps) {
+  if (!ctx) return fail(FQNM_ERR_ARG, "ctx is NULL");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned by an earlier device error");
+  if (n_steps < 0) return fail(FQNM_ERR_ARG, "n_steps must be >= 0");
+  fqnm_status st = ctx_advance(ctx, n_steps, ctx->buf, &ctx->cur, ctx->plan);
+  if (st) return st;
+  ctx->steps_done += n_steps;
+  if (ctx->borrowed && ctx->cur != 0) {
+    CTX_HIP(hipMemcpyAsync(ctx->buf[0], ctx->buf[1], ctx->state_bytes(),
+                           hipMemcpyDeviceToDevice, ctx->stream), "copy back");
+    ctx->cur = 0;
+  }
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_get_state(fqnm_ctx* ctx, void* q_host) {
+  if (!ctx || !q_host) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  CTX_HIP(hipMemcpyAsync(q_host, ctx->buf[ctx->cur], ctx->state_bytes(), hipMemcpyDeviceToHost,
+                         ctx->stream), "copy state");
+  CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_state_device(fqnm_ctx* ctx, void** d_q) {
+  if (!ctx || !d_q) return fail(FQNM_ERR_ARG, "NULL argument");
+  *d_q = ctx->buf[ctx->cur];
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u) {
+  if (!ctx || !d_u) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  CTX_HIP(launch_reconstruct(ctx->prob.itype, ctx->buf[ctx->cur], d_u, ctx->comp * ctx->prob.n,
+                             ctx->prob.delta, ctx->stream), "reconstruct");
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_reconstruct(fqnm_ctx* ctx, double* u_host) {
+  if (!ctx || !u_host) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  const int64_t total = ctx->comp * ctx->prob.n;
+  if (!ctx->d_u && hipMalloc(&ctx->d_u, sizeof(double) * total) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "hipMalloc of the field failed");
+  fqnm_status st = fqnm_reconstruct_device(ctx, ctx->d_u);
+  if (st) return st;
+  CTX_HIP(hipMemcpyAsync(u_host, ctx->d_u, sizeof(double) * total, hipMemcpyDeviceToHost,
+                         ctx->stream), "copy field");
+  CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
+  if (!ctx || !out) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  std::memset(out, 0, sizeof *out);
+  out->components = ctx->comp;
+  out->steps_done = ctx->steps_done;
+  const int64_t n = ctx->prob.n;
+  const int64_t nb = reduce_blocks(n);
+  if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
+  std::vector<ReducePartial> h(nb);
+  for (int c = 0; c < ctx->comp; ++c) {
+    const char* q = static_cast<const char*>(ctx->buf[ctx->cur]) + c * n * ctx->esize;
+    CTX_HIP(launch_reduce(ctx->prob.itype, q, n, ctx->prob.bc == FQNM_BC_PERIODIC, ctx->d_red,
+                          ctx->stream), "reduce");
+    CTX_HIP(hipMemcpyAsync(h.data(), ctx->d_red, sizeof(ReducePartial) * nb,
+                           hipMemcpyDeviceToHost, ctx->stream), "copy partials");
+    CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+    __int128 s = 0, tv = 0;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (auto& r : h) {
+      s += (static_cast<__int128>(r.sum_hi) << 64) | r.sum_lo;
+      tv += (static_cast<__int128>(r.tv_hi) << 64) | r.tv_lo;
+      lo = std::min(lo, r.qmin);
+      hi = std::max(hi, r.qmax);
+    }
+    out->sum_hi[c] = static_cast<int64_t>(s >> 64);
+    out->sum_lo[c] = static_cast<uint64_t>(s);
+    out->tv_hi[c] = static_cast<int64_t>(tv >> 64);
+    out->tv_lo[c] = static_cast<uint64_t>(tv);
+    out->qmin[c] = lo;
+    out->qmax[c] = hi;
+  }
+  long long led[3];
+  CTX_HIP(hipMemcpyAsync(led, ctx->d_ledger, sizeof led, hipMemcpyDeviceToHost, ctx->stream),
+          "copy ledger");
+  CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+  for (int c = 0; c < 3; ++c) out->ledger[c] = c < ctx->comp ? led[c] : 0;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out) {
+  if (!ctx || !out) return fail(FQNM_ERR_ARG, "NULL argument");
+  *out = ctx->plan;
+  if (ctx->euler) { out->kernel = K_STREAM; out->vec = 1; out->depth = 1; }
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
+  if (!ctx || !plan) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->euler) return fail(FQNM_ERR_UNSUPPORTED, "Euler contexts have a fixed plan");
+  fqnm_plan pl = ctx->plan;
+  if (plan->kernel == K_STREAM || plan->kernel == K_TBLOCK) pl.kernel = plan->kernel;
+  else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
+  if (plan->vec) pl.vec = plan->vec;
+  if (plan->depth) pl.depth = plan->depth;
+  if (!scalar_variant_available(ctx->prob.itype, ctx->pol, pl.kernel, pl.vec))
+    return fail(FQNM_ERR_ARG, "vec not available for this storage type");
+  if (pl.kernel == K_TBLOCK) {
+    if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth must be >= 1");
+    const int kh = scalar_halo(pl.vec, pl.depth);
+    if (64 * pl.vec - 2 * kh < pl.vec) return fail(FQNM_ERR_ARG, "depth too large for vec");
+  }
+  ctx->plan = pl;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
+  if (!ctx) return fail(FQNM_ERR_ARG, "ctx is NULL");
+  if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  if (ctx->euler) return FQNM_OK;
+  if (steps_per_trial < 1) return fail(FQNM_ERR_ARG, "steps_per_trial must be >= 1");
+  const size_t bytes = ctx->state_bytes();
+  void* sb[2] = {nullptr, nullptr};
+  long long* dled = nullptr;
+  if (hipMalloc(&sb[0], bytes) != hipSuccess || hipMalloc(&sb[1], bytes) != hipSuccess ||
+      hipMalloc(&dled, 3 * sizeof(long long)) != hipSuccess) {
+    if (sb[0]) (void)hipFree(sb[0]);
+    if (sb[1]) (void)hipFree(sb[1]);
+    if (dled) (void)hipFree(dled);
+    return fail(FQNM_ERR_OOM, "autotune scratch allocation failed");
+  }
+  long long* saved_ledger = ctx->d_ledger;
+  ctx->d_ledger = dled;  // trials must not touch the real ledger
+  std::vector<fqnm_plan> cand;
+  const bool i32 = ctx->prob.itype == FQNM_I32;
+  const int vecs32[] = {4, 8, 16}, vecs64[] = {2, 4, 8};
+  for (int v : (i32 ? vecs32 : vecs64)) {
+    const int PER = i32 ? 4 : 2;
+    if (v >= 2 * PER) cand.push_back({K_STREAM, v, 1, 0});
+    for (int d : {4, 8, 16, 32, 64, 96}) {
+      const int kh = scalar_halo(v, d);
+      if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
+    }
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  fqnm_plan bestp = ctx->plan;
+  fqnm_status st = FQNM_OK;
+  for (const fqnm_plan& c : cand) {
+    int cur = 0;
+    if (hipMemcpyAsync(sb[0], ctx->buf[ctx->cur], bytes, hipMemcpyDeviceToDevice, ctx->stream) !=
+        hipSuccess) { st = fail(FQNM_ERR_DEVICE, "autotune copy"); break; }
+    st = ctx_advance(ctx, std::min<int64_t>(steps_per_trial, 4 * c.depth), sb, &cur, c);  // warm
+    if (st) break;
+    (void)hipEventRecord(e0, ctx->stream);
+    st = ctx_advance(ctx, steps_per_trial, sb, &cur, c);
+    if (st) break;
+    (void)hipEventRecord(e1, ctx->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(FQNM_ERR_DEVICE, "autotune sync"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) { best = ms; bestp = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->d_ledger = saved_ledger;
+  (void)hipFree(sb[0]);
+  (void)hipFree(sb[1]);
+  (void)hipFree(dled);
+  if (st) return st;
+  bestp.eval = ctx->plan.eval;
+  ctx->plan = bestp;
+  store_plan(plan_key(ctx->prob, ctx->pol), bestp);
+  return FQNM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// fqnm_internal.h -- host-side declarations shared by the library's translation
+// units (kernel launchers and the runtime).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fqnm.h"
+#include "fqnm_device.h"
+
+namespace fqnm {
+
+enum : int { K_STREAM = 0, K_TBLOCK = 1 };
+
+// Per-block partial results of the reduction kernel (one record per block).
+struct ReducePartial {
+  uint64_t sum_lo;
+  int64_t sum_hi;
+  int64_t qmin;
+  int64_t qmax;
+  uint64_t tv_lo;
+  int64_t tv_hi;
+};
+
+// Single-grid scalar stepper: one launch advancing `ksteps` steps from src to
+// dst.  kernel = K_STREAM requires ksteps == 1.  Returns hipSuccess or the
+// launch error; hipErrorInvalidValue for an unavailable (itype, pol, vec).
+hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* src, void* dst,
+                         int64_t n, int bc, int ksteps, int khalo, const XParams& P,
+                         long long* d_ledger, hipStream_t s);
+bool scalar_variant_available(int itype, int pol, int kernel, int vec);
+int scalar_halo(int vec, int ksteps);  // halo width used by K_TBLOCK
+
+hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
+                            int64_t count, hipStream_t s);
+hipError_t launch_quantise(int itype, const double* u, void* q, int64_t n, double delta,
+                           int* d_err, hipStream_t s);
+hipError_t launch_reconstruct(int itype, const void* q, double* u, int64_t n, double delta,
+                              hipStream_t s);
+// Reduction over a state of n integers; writes reduce_blocks(n) partials.
+int64_t reduce_blocks(int64_t n);
+hipError_t launch_reduce(int itype, const void* q, int64_t n, int periodic, ReducePartial* out,
+                         hipStream_t s);
+
+// Euler (3 x int64, structure of arrays): one step per launch.
+struct EulerParams {
+  double delta;
+  double lambda;
+  double g1;  // gamma - 1
+  int fix;    // entropy fix on the acoustic waves
+};
+hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
+                             const EulerParams& E, long long* d_ledger, hipStream_t s);
+
+// Thread-local error message of the public ABI.
+void set_error(const std::string& msg);
+
+}  // namespace fqnm

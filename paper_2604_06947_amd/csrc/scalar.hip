@@ -1,0 +1,456 @@
+// scalar.hip -- single-grid kernels of the scalar integer transfer update.
+//
+// One step of Sec. 2 (eq:update_rule_conservative_form) is two phases: form the
+// interface count fluxes F_{i+1/2} = T(q_i, q_{i+1}), then q_i -= F_{i+1/2} - F_{i-1/2}
+// (Sec. 2.4).  Both phases are fused here; F never touches memory.
+//
+// Data layout: a state is a dense array of n integers (int32 or int64) in HBM,
+// 256-byte aligned, with a second array of the same size for ping-pong.  Each
+// lane owns `V` consecutive cells (16-byte vector loads/stores), a wavefront
+// owns 64*V consecutive cells, and the neighbour cells of a lane's first and
+// last cell arrive from the adjacent lanes by cross-lane moves.
+//
+// k_stream : one step per pass over memory.  Algorithmic traffic per
+//            cell-update: one state read + one state write (2*sizeof(IT) bytes).
+// k_tblock : temporal blocking.  A wavefront loads 64*V cells (its tile plus a
+//            halo of `khalo` cells on each side), advances them `ksteps` <= khalo
+//            steps in registers (the valid region shrinks by one cell per side
+//            per step), and stores the 64*V - 2*khalo interior cells.  Traffic
+//            per pass is that of one step; the redundant halo work is
+//            2*khalo/(64*V) of the tile.
+//
+// Boundaries (Sec. 2 grid; outflow by copied ghost cells):
+//   periodic: tile positions outside [0, n) load the wrapped cell, so a tile
+//             evolves a contiguous piece of the periodic extension.
+//   outflow : F_{-1/2} = T(q_0, q_0), F_{n-1/2} = T(q_{n-1}, q_{n-1}).  In k_tblock
+//             positions outside [0, n) are frozen (never updated) and the two
+//             boundary interfaces are evaluated from the in-domain cell.  The
+//             net boundary count F_{-1/2} - F_{n-1/2} of every step is added to a
+//             device ledger, so sum(q) - sum(q0) == ledger exactly.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fqnm_internal.h"
+
+namespace fqnm {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <typename IT, int V>
+__device__ __forceinline__ void load_vec(const IT* __restrict__ p, IT (&q)[V]) {
+  constexpr int PER = 16 / sizeof(IT);
+  static_assert(V % PER == 0, "V must fill whole 16-byte vectors");
+  const v4i* p4 = reinterpret_cast<const v4i*>(p);
+#pragma unroll
+  for (int c = 0; c < V / PER; ++c) {
+    v4i v = p4[c];
+    __builtin_memcpy(&q[c * PER], &v, 16);
+  }
+}
+
+template <typename IT, int V>
+__device__ __forceinline__ void store_vec(IT* __restrict__ p, const IT (&q)[V]) {
+  constexpr int PER = 16 / sizeof(IT);
+  v4i* p4 = reinterpret_cast<v4i*>(p);
+#pragma unroll
+  for (int c = 0; c < V / PER; ++c) {
+    v4i v;
+    __builtin_memcpy(&v, &q[c * PER], 16);
+    p4[c] = v;
+  }
+}
+
+// Ghost-cell index of position g for a one-step pass: periodic wrap or outflow copy.
+__device__ __forceinline__ int64_t ghost_index(int64_t g, int64_t n, int bc) {
+  if (g >= 0 && g < n) return g;
+  return bc == FQNM_BC_PERIODIC ? wrap_index(g, n) : clamp_index(g, n);
+}
+
+// ---------------------------------------------------------------------------
+// K1: one step per pass.
+// ---------------------------------------------------------------------------
+template <typename IT, int POL, int V>
+__global__ __launch_bounds__(256) void k_stream(const IT* __restrict__ src, IT* __restrict__ dst,
+                                                int64_t n, int bc, XParams P,
+                                                long long* __restrict__ ledger) {
+  const int lane = threadIdx.x & 63;
+  const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t base = (blk * 256 + threadIdx.x) * V;
+  const bool full = base + V <= n;
+  IT q[V];
+  if (full) {
+    load_vec<IT, V>(src + base, q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = src[ghost_index(base + j, n, bc)];
+  }
+  IT qn = lane_from_next<IT>(q[0]);
+  if (lane == 63) qn = src[ghost_index(base + V, n, bc)];
+  IT F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) F[j] = transfer<IT, POL>(P, q[j], j + 1 < V ? q[j + 1] : qn);
+  IT Fl = lane_from_prev<IT>(F[V - 1]);
+  if (lane == 0) Fl = transfer<IT, POL>(P, src[ghost_index(base - 1, n, bc)], q[0]);
+  IT out[V];
+  out[0] = wsub<IT>(q[0], wsub<IT>(F[0], Fl));
+#pragma unroll
+  for (int j = 1; j < V; ++j) out[j] = wsub<IT>(q[j], wsub<IT>(F[j], F[j - 1]));
+  if (full) {
+    store_vec<IT, V>(dst + base, out);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (base + j < n) dst[base + j] = out[j];
+  }
+  if (bc == FQNM_BC_OUTFLOW) {
+    long long led = 0;
+    if (base == 0) led += static_cast<long long>(Fl);
+    if (base <= n - 1 && n - 1 < base + V) {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (base + j == n - 1) led -= static_cast<long long>(F[j]);
+    }
+    if (led != 0) atomicAdd(reinterpret_cast<unsigned long long*>(ledger),
+                            static_cast<unsigned long long>(led));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: temporal blocking in registers.
+// ---------------------------------------------------------------------------
+template <typename IT, int POL, int V>
+__device__ __forceinline__ void tb_step_plain(const XParams& P, IT (&q)[V]) {
+  IT qn = lane_from_next<IT>(q[0]);
+  IT F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) F[j] = transfer<IT, POL>(P, q[j], j + 1 < V ? q[j + 1] : qn);
+  IT Fl = lane_from_prev<IT>(F[V - 1]);
+  q[0] = wsub<IT>(q[0], wsub<IT>(F[0], Fl));
+#pragma unroll
+  for (int j = 1; j < V; ++j) q[j] = wsub<IT>(q[j], wsub<IT>(F[j], F[j - 1]));
+}
+
+// Outflow tile touching a domain end: boundary interfaces use the in-domain
+// cell on both sides, positions outside [0, n) stay frozen.
+template <typename IT, int POL, int V>
+__device__ __forceinline__ void tb_step_outflow(const XParams& P, IT (&q)[V], int64_t g0,
+                                                int64_t n, bool own_right, long long& led) {
+  IT qn = lane_from_next<IT>(q[0]);
+  IT F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int64_t g = g0 + j;
+    IT qL = q[j];
+    IT qR = j + 1 < V ? q[j + 1] : qn;
+    if (g == -1) qL = qR;
+    if (g == n - 1) qR = qL;
+    F[j] = transfer<IT, POL>(P, qL, qR);
+    if (g == -1) led += static_cast<long long>(F[j]);
+    if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
+  }
+  IT Fl = lane_from_prev<IT>(F[V - 1]);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int64_t g = g0 + j;
+    IT d = wsub<IT>(F[j], j == 0 ? Fl : F[j - 1]);
+    if (g >= 0 && g < n) q[j] = wsub<IT>(q[j], d);
+  }
+}
+
+template <typename IT, int POL, int V>
+__global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* __restrict__ dst,
+                                                int64_t n, int bc, int ksteps, int khalo,
+                                                int64_t ntiles, XParams P,
+                                                long long* __restrict__ ledger) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= ntiles) return;  // the whole wavefront leaves together
+  const int64_t T = 64 * V - 2 * khalo;
+  const int64_t tstart = tile * T;
+  const int64_t wstart = tstart - khalo;
+  const int64_t g0 = wstart + static_cast<int64_t>(lane) * V;
+  const bool inside = wstart >= 0 && wstart + 64 * V <= n;  // wavefront-uniform
+  IT q[V];
+  if (inside) {
+    load_vec<IT, V>(src + g0, q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = src[ghost_index(g0 + j, n, bc)];
+  }
+  long long led = 0;
+  if (inside || bc == FQNM_BC_PERIODIC) {
+    for (int s = 0; s < ksteps; ++s) tb_step_plain<IT, POL, V>(P, q);
+  } else {
+    const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
+    for (int s = 0; s < ksteps; ++s) tb_step_outflow<IT, POL, V>(P, q, g0, n, own_right, led);
+  }
+  const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;
+  if (lane >= lane_lo && lane < lane_hi) {
+    if (g0 + V <= n) {
+      store_vec<IT, V>(dst + g0, q);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (g0 + j < n) dst[g0 + j] = q[j];
+    }
+  }
+  if (led != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
+}
+
+// ---------------------------------------------------------------------------
+// Off-loop kernels: LUT construction, quantisation, reconstruction, reduction.
+// ---------------------------------------------------------------------------
+template <typename IT, int POL>
+__global__ void k_lut_build(XParams P, typename LutEntry<IT>::T* __restrict__ lut, int64_t lo,
+                            int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    IT q = static_cast<IT>(lo + i);
+    typename LutEntry<IT>::T e;
+    e.x = split_phi<IT, POL>(P, q, true);
+    e.y = split_phi<IT, POL>(P, q, false);
+    lut[i] = e;
+  }
+}
+
+// q_i = rint(u_i / delta) (eq:quantisation); IEEE division.  Values outside
+// the storage range (or not exactly convertible to FP64) raise *err.
+template <typename IT>
+__global__ void k_quantise(const double* __restrict__ u, IT* __restrict__ q, int64_t n,
+                           double delta, double lim, int* err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double r = rint(u[i] / delta);
+    bool ok = fabs(r) <= lim;
+    if (!ok) atomicOr(err, 1);
+    q[i] = ok ? static_cast<IT>(r) : IT(0);
+  }
+}
+
+// u_i = delta * q_i (eq:reconstruction_operator).
+template <typename IT>
+__global__ void k_reconstruct(const IT* __restrict__ q, double* __restrict__ u, int64_t n,
+                              double delta) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    u[i] = delta * static_cast<double>(q[i]);
+}
+
+constexpr int RED_THREADS = 256;
+constexpr int64_t RED_CELLS_PER_BLOCK = 256 * 64;
+
+// Exact sum (128-bit), min, max and total variation of one state.
+template <typename IT>
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(const IT* __restrict__ q, int64_t n,
+                                                        int periodic,
+                                                        ReducePartial* __restrict__ out) {
+  __shared__ __int128 s_sum[RED_THREADS];
+  __shared__ __int128 s_tv[RED_THREADS];
+  __shared__ int64_t s_min[RED_THREADS];
+  __shared__ int64_t s_max[RED_THREADS];
+  const int64_t b0 = blockIdx.x * RED_CELLS_PER_BLOCK;
+  const int64_t b1 = b0 + RED_CELLS_PER_BLOCK < n ? b0 + RED_CELLS_PER_BLOCK : n;
+  __int128 sum = 0, tv = 0;
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += RED_THREADS) {
+    int64_t v = static_cast<int64_t>(q[i]);
+    sum += v;
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
+    int64_t w;
+    bool has = true;
+    if (i + 1 < n) w = static_cast<int64_t>(q[i + 1]);
+    else if (periodic && n > 1) w = static_cast<int64_t>(q[0]);
+    else { has = false; w = v; }
+    if (has) {
+      __int128 d = static_cast<__int128>(w) - v;
+      tv += d < 0 ? -d : d;
+    }
+  }
+  s_sum[threadIdx.x] = sum;
+  s_tv[threadIdx.x] = tv;
+  s_min[threadIdx.x] = mn;
+  s_max[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+      s_tv[threadIdx.x] += s_tv[threadIdx.x + w];
+      s_min[threadIdx.x] = s_min[threadIdx.x + w] < s_min[threadIdx.x] ? s_min[threadIdx.x + w]
+                                                                       : s_min[threadIdx.x];
+      s_max[threadIdx.x] = s_max[threadIdx.x + w] > s_max[threadIdx.x] ? s_max[threadIdx.x + w]
+                                                                       : s_max[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ReducePartial r;
+    r.sum_lo = static_cast<uint64_t>(s_sum[0]);
+    r.sum_hi = static_cast<int64_t>(s_sum[0] >> 64);
+    r.tv_lo = static_cast<uint64_t>(s_tv[0]);
+    r.tv_hi = static_cast<int64_t>(s_tv[0] >> 64);
+    r.qmin = s_min[0];
+    r.qmax = s_max[0];
+    out[blockIdx.x] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename IT, int POL, int V>
+hipError_t do_launch(int kernel, const void* src, void* dst, int64_t n, int bc, int ksteps,
+                     int khalo, const XParams& P, long long* d_ledger, hipStream_t s) {
+  const IT* a = static_cast<const IT*>(src);
+  IT* b = static_cast<IT*>(dst);
+  if (kernel == K_STREAM) {
+    const int64_t threads = (n + V - 1) / V;
+    const int64_t blocks = (threads + 255) / 256;
+    k_stream<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, b, n, bc, P, d_ledger);
+  } else {
+    const int64_t T = 64 * V - 2 * khalo;
+    const int64_t ntiles = (n + T - 1) / T;
+    const int64_t blocks = (ntiles + 3) / 4;
+    k_tblock<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, b, n, bc, ksteps, khalo,
+                                                                       ntiles, P, d_ledger);
+  }
+  return hipGetLastError();
+}
+
+template <typename IT, int POL>
+hipError_t by_vec(int kernel, int vec, const void* src, void* dst, int64_t n, int bc, int ksteps,
+                  int khalo, const XParams& P, long long* d_ledger, hipStream_t s) {
+  if constexpr (sizeof(IT) == 4) {
+    switch (vec) {
+      case 4: return do_launch<IT, POL, 4>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      case 8: return do_launch<IT, POL, 8>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      case 16: return do_launch<IT, POL, 16>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (vec) {
+      case 2: return do_launch<IT, POL, 2>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      case 4: return do_launch<IT, POL, 4>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      case 8: return do_launch<IT, POL, 8>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+template <typename IT>
+hipError_t by_pol(int pol, int kernel, int vec, const void* src, void* dst, int64_t n, int bc,
+                  int ksteps, int khalo, const XParams& P, long long* d_ledger, hipStream_t s) {
+#define FQNM_POL_CASE(p) \
+  case p: return by_vec<IT, p>(kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+  switch (pol) {
+    FQNM_POL_CASE(P_UPWIND_POS)
+    FQNM_POL_CASE(P_UPWIND_NEG)
+    FQNM_POL_CASE(P_EO)
+    FQNM_POL_CASE(P_GODUNOV)
+    FQNM_POL_CASE(P_MURMAN_ROE)
+    FQNM_POL_CASE(P_LF_LINEAR)
+    FQNM_POL_CASE(P_LF_BURGERS)
+    FQNM_POL_CASE(P_LUT)
+    default: return hipErrorInvalidValue;
+  }
+#undef FQNM_POL_CASE
+}
+
+unsigned grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+bool scalar_variant_available(int itype, int pol, int kernel, int vec) {
+  if (pol < 0 || pol >= P_COUNT || (kernel != K_STREAM && kernel != K_TBLOCK)) return false;
+  if (itype == FQNM_I32) return vec == 4 || vec == 8 || vec == 16;
+  if (itype == FQNM_I64) return vec == 2 || vec == 4 || vec == 8;
+  return false;
+}
+
+int scalar_halo(int vec, int ksteps) {
+  // smallest multiple of vec that is >= ksteps (whole halo lanes)
+  return ((ksteps + vec - 1) / vec) * vec;
+}
+
+hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* src, void* dst,
+                         int64_t n, int bc, int ksteps, int khalo, const XParams& P,
+                         long long* d_ledger, hipStream_t s) {
+  if (!scalar_variant_available(itype, pol, kernel, vec)) return hipErrorInvalidValue;
+  if (kernel == K_STREAM && ksteps != 1) return hipErrorInvalidValue;
+  if (kernel == K_TBLOCK && (khalo < ksteps || khalo % vec != 0 || 64 * vec - 2 * khalo <= 0))
+    return hipErrorInvalidValue;
+  if (itype == FQNM_I32)
+    return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+  return by_pol<int64_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+}
+
+hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
+                            int64_t count, hipStream_t s) {
+  const unsigned g = grid_for(count, 256);
+#define FQNM_LUT_CASE(IT, p)                                                                 \
+  case p:                                                                                    \
+    k_lut_build<IT, p><<<g, 256, 0, s>>>(P, static_cast<typename LutEntry<IT>::T*>(lut), lo, \
+                                         count);                                             \
+    return hipGetLastError();
+  if (itype == FQNM_I32) {
+    switch (pol) {
+      FQNM_LUT_CASE(int32_t, P_UPWIND_POS)
+      FQNM_LUT_CASE(int32_t, P_UPWIND_NEG)
+      FQNM_LUT_CASE(int32_t, P_EO)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (pol) {
+    FQNM_LUT_CASE(int64_t, P_UPWIND_POS)
+    FQNM_LUT_CASE(int64_t, P_UPWIND_NEG)
+    FQNM_LUT_CASE(int64_t, P_EO)
+    default: return hipErrorInvalidValue;
+  }
+#undef FQNM_LUT_CASE
+}
+
+hipError_t launch_quantise(int itype, const double* u, void* q, int64_t n, double delta,
+                           int* d_err, hipStream_t s) {
+  const unsigned g = grid_for(n, 256);
+  if (itype == FQNM_I32)
+    k_quantise<int32_t><<<g, 256, 0, s>>>(u, static_cast<int32_t*>(q), n, delta, 2147483647.0,
+                                          d_err);
+  else
+    k_quantise<int64_t><<<g, 256, 0, s>>>(u, static_cast<int64_t*>(q), n, delta,
+                                          4503599627370495.0, d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(int itype, const void* q, double* u, int64_t n, double delta,
+                              hipStream_t s) {
+  const unsigned g = grid_for(n, 256);
+  if (itype == FQNM_I32)
+    k_reconstruct<int32_t><<<g, 256, 0, s>>>(static_cast<const int32_t*>(q), u, n, delta);
+  else
+    k_reconstruct<int64_t><<<g, 256, 0, s>>>(static_cast<const int64_t*>(q), u, n, delta);
+  return hipGetLastError();
+}
+
+int64_t reduce_blocks(int64_t n) { return (n + RED_CELLS_PER_BLOCK - 1) / RED_CELLS_PER_BLOCK; }
+
+hipError_t launch_reduce(int itype, const void* q, int64_t n, int periodic, ReducePartial* out,
+                         hipStream_t s) {
+  const unsigned g = static_cast<unsigned>(reduce_blocks(n));
+  if (itype == FQNM_I32)
+    k_reduce<int32_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int32_t*>(q), n, periodic, out);
+  else
+    k_reduce<int64_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int64_t*>(q), n, periodic, out);
+  return hipGetLastError();
+}
+
+}  // namespace fqnm

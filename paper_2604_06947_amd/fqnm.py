@@ -1,0 +1,335 @@
+"""Thin ctypes binding of libfqnm.so (include/fqnm.h), same names as the C ABI.
+
+Only argument marshalling happens here: every step of the method runs in the
+HIP library.  Loading fails loudly when the library has not been built; there
+is no CPU fallback.  Host arrays are numpy arrays; device pointers and streams
+are plain integers (e.g. ``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfqnm.so")
+
+ABI_VERSION = 1
+
+# fqnm_status
+OK, ERR_ARG, ERR_CFL, ERR_RANGE, ERR_OOM, ERR_DEVICE, ERR_STATE, ERR_BUSY, ERR_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_CFL", -3: "ERR_RANGE", -4: "ERR_OOM",
+                -5: "ERR_DEVICE", -6: "ERR_STATE", -7: "ERR_BUSY", -8: "ERR_UNSUPPORTED"}
+
+# fqnm_flux, fqnm_bc, fqnm_itype, fqnm_eval
+FLUX_UPWIND, FLUX_BURGERS_EO, FLUX_BURGERS_GODUNOV, FLUX_LF_LINEAR, FLUX_LF_BURGERS = 0, 1, 2, 3, 4
+FLUX_EULER_ROE, FLUX_EULER_ROE_EF, FLUX_BURGERS_MURMAN_ROE = 5, 6, 7
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+I32, I64 = 0, 1
+EVAL_AUTO, EVAL_DIRECT, EVAL_LUT = 0, 1, 2
+KERNEL_STREAM, KERNEL_TBLOCK = 0, 1
+
+EXPORTED = [
+    "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",
+    "fqnm_create_on_device", "fqnm_step", "fqnm_get_state", "fqnm_state_device",
+    "fqnm_reconstruct", "fqnm_reconstruct_device", "fqnm_invariants_get", "fqnm_get_plan",
+    "fqnm_set_plan", "fqnm_autotune", "fqnm_destroy", "fqnm_batch_create", "fqnm_batch_reset",
+    "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
+    "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
+    "fqnm_server_drain", "fqnm_server_stats_get", "fqnm_server_now", "fqnm_server_destroy",
+]
+
+
+class FqnmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fqnm_problem(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("flux", C.c_int32), ("bc", C.c_int32),
+                ("itype", C.c_int32), ("eval", C.c_int32), ("reserved", C.c_int32),
+                ("a", C.c_double), ("alpha", C.c_double), ("gamma", C.c_double),
+                ("delta", C.c_double), ("dx", C.c_double), ("lambda_", C.c_double),
+                ("n", C.c_int64)]
+
+
+class fqnm_invariants(C.Structure):
+    _fields_ = [("components", C.c_int32), ("reserved", C.c_int32), ("steps_done", C.c_int64),
+                ("sum_hi", C.c_int64 * 3), ("sum_lo", C.c_uint64 * 3), ("qmin", C.c_int64 * 3),
+                ("qmax", C.c_int64 * 3), ("tv_hi", C.c_int64 * 3), ("tv_lo", C.c_uint64 * 3),
+                ("ledger", C.c_int64 * 3)]
+
+
+class fqnm_plan(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("vec", C.c_int32), ("depth", C.c_int32),
+                ("eval", C.c_int32)]
+
+
+class fqnm_completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("components", C.c_int32),
+                ("n", C.c_int64), ("steps", C.c_int64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class fqnm_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("queued", C.c_int64), ("active", C.c_int64), ("ticks", C.c_int64),
+                ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64),
+                ("cell_updates", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfqnm.so; raise if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        P = C.POINTER(fqnm_problem)
+        sig = {
+            "fqnm_last_error": ([], C.c_char_p),
+            "fqnm_version": ([], C.c_char_p),
+            "fqnm_create": ([P, vp, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_create_from_field": ([P, vp, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_create_on_device": ([P, vp, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_step": ([vp, i64], C.c_int),
+            "fqnm_get_state": ([vp, vp], C.c_int),
+            "fqnm_state_device": ([vp, C.POINTER(vp)], C.c_int),
+            "fqnm_reconstruct": ([vp, vp], C.c_int),
+            "fqnm_reconstruct_device": ([vp, vp], C.c_int),
+            "fqnm_invariants_get": ([vp, C.POINTER(fqnm_invariants)], C.c_int),
+            "fqnm_get_plan": ([vp, C.POINTER(fqnm_plan)], C.c_int),
+            "fqnm_set_plan": ([vp, C.POINTER(fqnm_plan)], C.c_int),
+            "fqnm_autotune": ([vp, i64], C.c_int),
+            "fqnm_destroy": ([vp], C.c_int),
+            "fqnm_batch_create": ([P, C.POINTER(vp), C.POINTER(i64), i32, vp, C.POINTER(vp)],
+                                  C.c_int),
+            "fqnm_batch_reset": ([vp], C.c_int),
+            "fqnm_batch_run": ([vp], C.c_int),
+            "fqnm_batch_run_per_instance": ([vp], C.c_int),
+            "fqnm_batch_get_state": ([vp, i32, vp], C.c_int),
+            "fqnm_batch_destroy": ([vp], C.c_int),
+            "fqnm_server_create": ([C.c_size_t, i32, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_server_submit": ([vp, P, vp, i64, vp, C.POINTER(C.c_uint64)], C.c_int),
+            "fqnm_server_poll": ([vp, C.POINTER(fqnm_completion), i32, C.POINTER(i32)], C.c_int),
+            "fqnm_server_drain": ([vp, C.c_double], C.c_int),
+            "fqnm_server_stats_get": ([vp, C.POINTER(fqnm_server_stats)], C.c_int),
+            "fqnm_server_now": ([], C.c_double),
+            "fqnm_fp64_selfcheck": ([vp, vp, vp, vp, i64, vp], C.c_int),
+            "fqnm_server_destroy": ([vp], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise FqnmError(st, lib().fqnm_last_error().decode())
+
+
+def make_problem(flux, delta, lam, n, bc=BC_PERIODIC, itype=I32, eval_=EVAL_AUTO, a=1.0,
+                 alpha=0.0, gamma=1.4, dx=None):
+    return fqnm_problem(ABI_VERSION, flux, bc, itype, eval_, 0, a, alpha, gamma, delta,
+                        dx if dx is not None else 1.0 / n, lam, n)
+
+
+def _np_itype(prob):
+    return np.int32 if prob.itype == I32 else np.int64
+
+
+def _components(prob):
+    return 3 if prob.flux in (FLUX_EULER_ROE, FLUX_EULER_ROE_EF) else 1
+
+
+def fqnm_last_error():
+    return lib().fqnm_last_error().decode()
+
+
+def fqnm_version():
+    return lib().fqnm_version().decode()
+
+
+def fqnm_create(prob, q0, stream=None):
+    q0 = np.ascontiguousarray(q0, dtype=_np_itype(prob)).ravel()
+    if q0.size != _components(prob) * prob.n:
+        raise ValueError("q0 has the wrong size")
+    h = C.c_void_p()
+    _check(lib().fqnm_create(C.byref(prob), q0.ctypes.data, stream, C.byref(h)))
+    return h
+
+
+def fqnm_create_from_field(prob, u0, stream=None):
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    if u0.size != _components(prob) * prob.n:
+        raise ValueError("u0 has the wrong size")
+    h = C.c_void_p()
+    _check(lib().fqnm_create_from_field(C.byref(prob), u0.ctypes.data, stream, C.byref(h)))
+    return h
+
+
+def fqnm_create_on_device(prob, d_q: int, stream=None):
+    h = C.c_void_p()
+    _check(lib().fqnm_create_on_device(C.byref(prob), C.c_void_p(d_q), stream, C.byref(h)))
+    return h
+
+
+def fqnm_step(h, n_steps):
+    _check(lib().fqnm_step(h, int(n_steps)))
+
+
+def fqnm_get_state(h, prob):
+    out = np.empty(_components(prob) * prob.n, dtype=_np_itype(prob))
+    _check(lib().fqnm_get_state(h, out.ctypes.data))
+    return out if _components(prob) == 1 else out.reshape(3, prob.n)
+
+
+def fqnm_state_device(h):
+    p = C.c_void_p()
+    _check(lib().fqnm_state_device(h, C.byref(p)))
+    return p.value
+
+
+def fqnm_reconstruct(h, prob):
+    out = np.empty(_components(prob) * prob.n, dtype=np.float64)
+    _check(lib().fqnm_reconstruct(h, out.ctypes.data))
+    return out if _components(prob) == 1 else out.reshape(3, prob.n)
+
+
+def fqnm_reconstruct_device(h, d_u: int):
+    _check(lib().fqnm_reconstruct_device(h, C.c_void_p(d_u)))
+
+
+def _i128(hi, lo):
+    return (int(hi) << 64) + int(lo)
+
+
+def fqnm_invariants_get(h):
+    inv = fqnm_invariants()
+    _check(lib().fqnm_invariants_get(h, C.byref(inv)))
+    k = inv.components
+    return {"components": k, "steps_done": inv.steps_done,
+            "sum": [_i128(inv.sum_hi[c], inv.sum_lo[c]) for c in range(k)],
+            "min": [inv.qmin[c] for c in range(k)], "max": [inv.qmax[c] for c in range(k)],
+            "tv": [_i128(inv.tv_hi[c], inv.tv_lo[c]) for c in range(k)],
+            "ledger": [inv.ledger[c] for c in range(k)]}
+
+
+def fqnm_get_plan(h):
+    p = fqnm_plan()
+    _check(lib().fqnm_get_plan(h, C.byref(p)))
+    return {"kernel": p.kernel, "vec": p.vec, "depth": p.depth, "eval": p.eval}
+
+
+def fqnm_set_plan(h, kernel=0, vec=0, depth=0):
+    p = fqnm_plan(kernel, vec, depth, 0)
+    _check(lib().fqnm_set_plan(h, C.byref(p)))
+
+
+def fqnm_autotune(h, steps_per_trial):
+    _check(lib().fqnm_autotune(h, int(steps_per_trial)))
+
+
+def fqnm_destroy(h):
+    _check(lib().fqnm_destroy(h))
+
+
+def fqnm_fp64_selfcheck(d_a: int, d_b: int, d_sqrt: int, d_div: int, n: int, stream=None):
+    _check(lib().fqnm_fp64_selfcheck(C.c_void_p(d_a), C.c_void_p(d_b), C.c_void_p(d_sqrt),
+                                     C.c_void_p(d_div), int(n), stream))
+
+
+# --------------------------------------------------------------------------
+# batching
+# --------------------------------------------------------------------------
+def fqnm_batch_create(probs, q0s, steps, stream=None):
+    count = len(probs)
+    parr = (fqnm_problem * count)(*probs)
+    keep = [np.ascontiguousarray(q, dtype=_np_itype(p)).ravel() for p, q in zip(probs, q0s)]
+    ptrs = (C.c_void_p * count)(*[k.ctypes.data for k in keep])
+    st = (C.c_int64 * count)(*[int(s) for s in steps])
+    h = C.c_void_p()
+    _check(lib().fqnm_batch_create(parr, ptrs, st, count, stream, C.byref(h)))
+    return h
+
+
+def fqnm_batch_reset(h):
+    _check(lib().fqnm_batch_reset(h))
+
+
+def fqnm_batch_run(h):
+    _check(lib().fqnm_batch_run(h))
+
+
+def fqnm_batch_run_per_instance(h):
+    _check(lib().fqnm_batch_run_per_instance(h))
+
+
+def fqnm_batch_get_state(h, idx, prob):
+    out = np.empty(prob.n, dtype=_np_itype(prob))
+    _check(lib().fqnm_batch_get_state(h, int(idx), out.ctypes.data))
+    return out
+
+
+def fqnm_batch_destroy(h):
+    _check(lib().fqnm_batch_destroy(h))
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+def fqnm_server_create(budget_bytes, tick_steps, stream=None):
+    h = C.c_void_p()
+    _check(lib().fqnm_server_create(int(budget_bytes), int(tick_steps), stream, C.byref(h)))
+    return h
+
+
+def fqnm_server_submit(h, prob, q0, n_steps, out):
+    """out: a preallocated numpy array that receives the final state; it must
+    stay alive until the request is reported complete."""
+    q0 = np.ascontiguousarray(q0, dtype=_np_itype(prob)).ravel()
+    if not (out.flags["C_CONTIGUOUS"] and out.size == q0.size and out.dtype == q0.dtype):
+        raise ValueError("out must be a contiguous array shaped like q0")
+    rid = C.c_uint64()
+    _check(lib().fqnm_server_submit(h, C.byref(prob), q0.ctypes.data, int(n_steps),
+                                    out.ctypes.data, C.byref(rid)))
+    return rid.value
+
+
+def fqnm_server_poll(h, max_items=256):
+    buf = (fqnm_completion * max_items)()
+    n = C.c_int32()
+    _check(lib().fqnm_server_poll(h, buf, max_items, C.byref(n)))
+    return [{"id": c.id, "status": c.status, "n": c.n, "steps": c.steps,
+             "components": c.components, "t_submit": c.t_submit, "t_admit": c.t_admit,
+             "t_done": c.t_done} for c in buf[:n.value]]
+
+
+def fqnm_server_drain(h, timeout_s=600.0):
+    _check(lib().fqnm_server_drain(h, float(timeout_s)))
+
+
+def fqnm_server_stats_get(h):
+    s = fqnm_server_stats()
+    _check(lib().fqnm_server_stats_get(h, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in fqnm_server_stats._fields_}
+
+
+def fqnm_server_now():
+    return lib().fqnm_server_now()
+
+
+def fqnm_server_destroy(h):
+    _check(lib().fqnm_server_destroy(h))

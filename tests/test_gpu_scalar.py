@@ -1,0 +1,281 @@
+"""GPU parity of the single-grid stepper against the CPU oracle, through the C ABI.
+
+Integer states must match bit for bit (the method is deterministic integer
+arithmetic with fixed-order FP64 maps, so there is exactly one correct
+trajectory).  Sizes span several tiles and a ragged tail; every launch plan
+must give the same bytes, which also catches halo and race mistakes.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_06947_amd import fqnm as F
+from paper_2604_06947_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KIND_F2O = {F.FLUX_UPWIND: O.UPWIND, F.FLUX_BURGERS_EO: O.BURGERS_EO,
+            F.FLUX_BURGERS_GODUNOV: O.BURGERS_GODUNOV, F.FLUX_LF_LINEAR: O.LF_LINEAR,
+            F.FLUX_LF_BURGERS: O.LF_BURGERS, F.FLUX_BURGERS_MURMAN_ROE: O.BURGERS_MURMAN_ROE,
+            F.FLUX_EULER_ROE: O.EULER_ROE, F.FLUX_EULER_ROE_EF: O.EULER_ROE_EF}
+
+PLANS32 = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_STREAM, 16, 1),
+           (F.KERNEL_TBLOCK, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 8, 8),
+           (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96)]
+PLANS64 = [(F.KERNEL_STREAM, 2, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_TBLOCK, 2, 2),
+           (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    F.lib()
+
+
+def gpu_run(prob, q0=None, u0=None, steps=0, plan=None):
+    h = F.fqnm_create(prob, q0) if u0 is None else F.fqnm_create_from_field(prob, u0)
+    try:
+        if plan is not None:
+            F.fqnm_set_plan(h, *plan)
+        F.fqnm_step(h, steps)
+        q = F.fqnm_get_state(h, prob).astype(np.int64)
+        inv = F.fqnm_invariants_get(h)
+    finally:
+        F.fqnm_destroy(h)
+    return q, inv
+
+
+def oracle_problem(prob):
+    return O.Problem(KIND_F2O[prob.flux], prob.delta, prob.lambda_, bc=prob.bc,
+                     width=32 if prob.itype == F.I32 else 64, a=prob.a, alpha=prob.alpha,
+                     gamma=prob.gamma)
+
+
+def plans_for(itype):
+    return PLANS32 if itype == F.I32 else PLANS64
+
+
+# ---------------------------------------------------------------------------
+def test_w1_advection_square_every_plan():
+    w = W.w1_advection_square()
+    ref = O.step(O.Problem(O.UPWIND, w.delta, w.lam, width=32, a=1.0),
+                 O.quantise(w.u0, w.delta, 32), w.steps)
+    prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I32, a=1.0)
+    for plan in PLANS32:
+        q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
+        assert np.array_equal(q, ref), plan
+        assert inv["sum"][0] == int(ref.sum())
+
+
+def make_case(flux, bc, itype, n, seed, a=1.0, alpha=0.0, lut=False):
+    u0 = W.random_smooth_step(n, seed=seed, b=0.1)
+    delta = 1e-4 if itype == F.I32 else 1e-7
+    umax = float(np.max(np.abs(u0)))
+    if flux == F.FLUX_UPWIND:
+        lam = 0.77 / abs(a)
+    elif flux in (F.FLUX_LF_LINEAR, F.FLUX_LF_BURGERS):
+        alpha = max(abs(a), umax) * 1.25 if flux == F.FLUX_LF_LINEAR else umax * 1.25
+        lam = 0.8 / alpha
+    else:
+        lam = 0.45 / umax
+    return u0, F.make_problem(flux, delta, lam, n, bc=bc, itype=itype,
+                              eval_=F.EVAL_LUT if lut else F.EVAL_DIRECT, a=a, alpha=alpha)
+
+
+KINDS = [(F.FLUX_UPWIND, 1.0, False), (F.FLUX_UPWIND, -0.9, False), (F.FLUX_UPWIND, 1.0, True),
+         (F.FLUX_BURGERS_EO, 1.0, False), (F.FLUX_BURGERS_EO, 1.0, True),
+         (F.FLUX_BURGERS_GODUNOV, 1.0, False), (F.FLUX_BURGERS_MURMAN_ROE, 1.0, False),
+         (F.FLUX_LF_LINEAR, 0.6, False), (F.FLUX_LF_BURGERS, 1.0, False)]
+
+
+@pytest.mark.parametrize("flux,a,lut", KINDS)
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+def test_kind_parity_all_plans(flux, a, lut, bc, itype):
+    n, steps = 5003, 150
+    u0, prob = make_case(flux, bc, itype, n, seed=100 + flux, a=a, lut=lut)
+    op = oracle_problem(prob)
+    q0 = O.quantise(u0, prob.delta, op.width)
+    ref, led = O.step(op, q0, steps, return_ledger=True)
+    for plan in plans_for(itype):
+        q, inv = gpu_run(prob, u0=u0, steps=steps, plan=plan)
+        assert np.array_equal(q, ref), plan
+        assert inv["ledger"][0] == led
+        assert inv["sum"][0] == int(ref.sum())
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 63, 64, 65, 127, 959, 960, 961, 1985])
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+def test_edge_sizes(n, bc):
+    for flux in (F.FLUX_UPWIND, F.FLUX_BURGERS_EO, F.FLUX_BURGERS_GODUNOV):
+        u0, prob = make_case(flux, bc, F.I32, n, seed=7 + n, lut=False)
+        op = oracle_problem(prob)
+        q0 = O.quantise(u0, prob.delta, 32)
+        for steps in (0, 1, 37):
+            ref = O.step(op, q0, steps)
+            for plan in [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_TBLOCK, 4, 4),
+                         (F.KERNEL_TBLOCK, 16, 32)]:
+                q, _ = gpu_run(prob, q0=q0.astype(np.int32), steps=steps, plan=plan)
+                assert np.array_equal(q, ref), (flux, steps, plan)
+
+
+def test_quantise_and_reconstruct_match_oracle():
+    rng = np.random.default_rng(5)
+    n = 10007
+    u0 = rng.uniform(-3, 3, n)
+    u0[:8] = np.array([2.5, 3.5, -2.5, -0.5, 0.5, 1.5, 7.25, -7.75]) * 2.0 ** -10  # ties
+    for itype, width in ((F.I32, 32), (F.I64, 64)):
+        delta = 2.0 ** -10
+        prob = F.make_problem(F.FLUX_UPWIND, delta, 0.5, n, itype=itype)
+        h = F.fqnm_create_from_field(prob, u0)
+        try:
+            q = F.fqnm_get_state(h, prob).astype(np.int64)
+            u = F.fqnm_reconstruct(h, prob)
+        finally:
+            F.fqnm_destroy(h)
+        assert np.array_equal(q, O.quantise(u0, delta, width))
+        assert np.array_equal(u, O.reconstruct(q, delta))
+
+
+def test_invariants_match_oracle():
+    u0, prob = make_case(F.FLUX_BURGERS_EO, F.BC_PERIODIC, F.I64, 70001, seed=9)
+    q0 = O.quantise(u0, prob.delta, 64)
+    h = F.fqnm_create(prob, q0)
+    try:
+        F.fqnm_step(h, 100)
+        inv = F.fqnm_invariants_get(h)
+        q = F.fqnm_get_state(h, prob)
+    finally:
+        F.fqnm_destroy(h)
+    ref = O.invariants(q, periodic=True)
+    assert inv["sum"][0] == ref["sum"] == int(q0.sum())
+    assert inv["min"][0] == ref["min"] and inv["max"][0] == ref["max"]
+    assert inv["tv"][0] == ref["tv"]
+    assert inv["steps_done"] == 100
+
+
+def test_checkpoint_resume_bitexact():
+    u0, prob = make_case(F.FLUX_BURGERS_EO, F.BC_OUTFLOW, F.I32, 20000, seed=3, lut=True)
+    qa, _ = gpu_run(prob, u0=u0, steps=333)
+    q1, _ = gpu_run(prob, u0=u0, steps=120)
+    qb, _ = gpu_run(prob, q0=q1.astype(np.int32), steps=213)
+    assert np.array_equal(qa, qb)
+
+
+def test_create_on_device_keeps_state_in_tensor():
+    import torch
+    u0, prob = make_case(F.FLUX_UPWIND, F.BC_PERIODIC, F.I32, 4099, seed=11)
+    q0 = O.quantise(u0, prob.delta, 32)
+    t = torch.tensor(q0.astype(np.int32), device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    h = F.fqnm_create_on_device(prob, t.data_ptr(), stream)
+    try:
+        F.fqnm_set_plan(h, F.KERNEL_TBLOCK, 8, 7)
+        F.fqnm_step(h, 45)  # an odd number of launches
+        torch.cuda.synchronize()
+        got = t.cpu().numpy().astype(np.int64)
+    finally:
+        F.fqnm_destroy(h)
+    assert np.array_equal(got, O.step(oracle_problem(prob), q0, 45))
+
+
+def test_autotune_then_parity():
+    w = W.w2_burgers_step(n=1 << 16, steps=300)
+    prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
+                          eval_=F.EVAL_LUT)
+    h = F.fqnm_create_from_field(prob, w.u0)
+    try:
+        F.fqnm_autotune(h, 64)
+        plan = F.fqnm_get_plan(h)
+        F.fqnm_step(h, w.steps)
+        q = F.fqnm_get_state(h, prob).astype(np.int64)
+        inv = F.fqnm_invariants_get(h)
+    finally:
+        F.fqnm_destroy(h)
+    assert plan["eval"] == F.EVAL_LUT and inv["steps_done"] == w.steps
+    ref = O.step(O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32),
+                 O.quantise(w.u0, w.delta, 32), w.steps)
+    assert np.array_equal(q, ref)
+
+
+@pytest.mark.parametrize("bad", ["cfl", "lut_godunov", "range", "abi", "euler_i32", "n0"])
+def test_create_rejects_invalid_problems(bad):
+    n = 100
+    q0 = np.zeros(n, np.int32)
+    prob = F.make_problem(F.FLUX_UPWIND, 1e-3, 0.5, n, itype=F.I32)
+    want = F.ERR_ARG
+    if bad == "cfl":
+        prob.lambda_ = 1.5
+        want = F.ERR_CFL
+    elif bad == "lut_godunov":
+        prob.flux = F.FLUX_BURGERS_GODUNOV
+        prob.eval = F.EVAL_LUT
+    elif bad == "range":
+        q0 = np.full(n, 2 ** 31 - 10, np.int32)
+        want = F.ERR_RANGE
+    elif bad == "abi":
+        prob.abi_version = 99
+    elif bad == "euler_i32":
+        prob.flux = F.FLUX_EULER_ROE
+        q0 = np.zeros(3 * n, np.int32)
+    elif bad == "n0":
+        prob.n = 0
+        q0 = np.zeros(0, np.int32)
+    with pytest.raises((F.FqnmError, ValueError)) as e:
+        F.fqnm_create(prob, q0)
+    if isinstance(e.value, F.FqnmError):
+        assert e.value.status == want
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: sampled cells against the oracle.  A cell after s
+# steps depends only on the 2s+1 cells around it, so the oracle steps that
+# window (any boundary) and its centre is exact.
+# ---------------------------------------------------------------------------
+def window_centre(op, q0, i, s):
+    n = q0.size
+    idx = np.arange(i - s, i + s + 1) % n
+    win = O.Problem(op.kind, op.delta, op.lam, bc=O.OUTFLOW, width=op.width, a=op.a,
+                    alpha=op.alpha)
+    return int(O.step(win, q0[idx], s)[s])
+
+
+def test_w2_burgers_full_size_sampled():
+    from paper_2604_06947_amd import plans
+    w = W.w2_burgers_step()
+    prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
+                          eval_=F.EVAL_LUT)
+    q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plans.BENCH_PLAN_W2)
+    q0 = O.quantise(w.u0, w.delta, 32)
+    op = O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32)
+    assert inv["sum"][0] == int(q0.sum())
+    assert q0.min() <= q.min() and q.max() <= q0.max()
+    rng = np.random.default_rng(2024)
+    xs = int(np.argmax(np.diff(q0) > 10000))  # near the seeded step
+    for i in [0, w.n - 1, xs, xs + 1] + list(rng.integers(0, w.n, 2)):
+        assert q[i] == window_centre(op, q0, int(i), w.steps), i
+
+
+@pytest.mark.parametrize("r", [1e-2, 1e-3, 1e-4])
+def test_w3_nyquist_full_size_sampled(r):
+    from paper_2604_06947_amd import plans
+    w = W.w3_nyquist_advection(r=r)
+    prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I64, a=1.0)
+    q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plans.BENCH_PLAN_W3)
+    q0 = O.quantise(w.u0, w.delta, 64)
+    assert inv["sum"][0] == int(q0.sum())
+    op = O.Problem(O.UPWIND, w.delta, w.lam, width=64, a=1.0)
+    rng = np.random.default_rng(int(1 / r))
+    for i in [0, 1, w.n - 1] + list(rng.integers(0, w.n, 5)):
+        assert q[i] == window_centre(op, q0, int(i), w.steps), i
+
+
+def test_w3_reduced_bitexact():
+    w = W.w3_nyquist_advection(r=1e-3, n=1 << 16, steps=300)
+    prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I64, a=1.0)
+    ref = O.step(O.Problem(O.UPWIND, w.delta, w.lam, width=64, a=1.0),
+                 O.quantise(w.u0, w.delta, 64), w.steps)
+    for plan in PLANS64:
+        q, _ = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
+        assert np.array_equal(q, ref), plan
