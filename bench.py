@@ -99,6 +99,51 @@ def time_solver(S, steps_per_solve, K, W):
     return (t1 - t0) / K, step_s
 
 
+def bench_batch(F, W, stream, reps=3):
+    """4096 instances (advection/Burgers, 256..65536 cells, 500..5000 steps) in
+    one batched run against the one-instance-at-a-time loop on the same GPU."""
+    import torch
+    log("[bench] W4 generating 4096 instances")
+    ws = W.w4_batch()
+    sizes = [w.n for w in ws]
+    q_all = F.fqnm_quantise(np.concatenate([w.u0 for w in ws]), ws[0].delta, F.I32, stream)
+    q0s = np.split(q_all, np.cumsum(sizes)[:-1])
+    probs = [F.make_problem(w.kind, w.delta, w.lam, w.n, itype=F.I32, a=w.a) for w in ws]
+    steps = [w.steps for w in ws]
+    work = float(sum(n * s for n, s in zip(sizes, steps)))
+    h = F.fqnm_batch_create(probs, q0s, steps, stream)
+    try:
+        F.fqnm_batch_reset(h)
+        F.fqnm_batch_run(h)  # warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            F.fqnm_batch_reset(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F.fqnm_batch_run(h)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        log(f"[bench] W4 batched {min(ts)*1e3:.1f} ms; per-instance loop follows")
+        F.fqnm_batch_reset(h)
+        F.fqnm_batch_run_per_instance(h)  # creates the per-instance contexts, warm-up
+        torch.cuda.synchronize()
+        F.fqnm_batch_reset(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fqnm_batch_run_per_instance(h)
+        torch.cuda.synchronize()
+        t_solo = time.perf_counter() - t0
+    finally:
+        F.fqnm_batch_destroy(h)
+    t_b = float(np.median(ts))
+    return {"w4_batch": {"instances": len(ws), "cell_updates": work,
+                         "batched_ms": t_b * 1e3, "batched_cell_updates_per_s": work / t_b,
+                         "per_instance_ms": t_solo * 1e3,
+                         "per_instance_cell_updates_per_s": work / t_solo,
+                         "speedup_vs_per_instance": t_solo / t_b}}
+
+
 def cpu_oracle_rate(w, steps):
     import oracle as O
     op = O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32)
@@ -198,6 +243,9 @@ def main():
                     "cell_updates_per_s": rate, "ms_per_solve": sec3 * 1e3,
                     "kernel_GBps_algorithmic": ach3, "frac_of_hbm": ach3 / HBM_PEAK_GBS,
                     "frac_of_int64_roofline": rate / (HBM_PEAK_GBS * 1e9 / 16.0)}
+    # ---------------- batched: 4096 independent instances --------------------------
+    if not args.no_extras and args.only in ("", "batch"):
+        extras.update(bench_batch(F, W, stream))
     # ---------------- CPU oracle baseline --------------------------------------------
     if not args.no_cpu:
         csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "600"))

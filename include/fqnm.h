@@ -121,9 +121,11 @@ typedef struct {
 } fqnm_invariants;
 
 /* Launch plan of the single-grid stepper.  kernel 0 = one step per pass
- * ("stream"), 1 = temporal blocking: every wavefront keeps a tile of
- * 64*vec cells in registers and advances it `depth` steps per pass over
- * memory.  Zero fields mean "choose". */
+ * ("stream"); 1 = temporal blocking: every wavefront keeps a tile of 64*vec
+ * consecutive cells in registers (vec consecutive cells per lane) and
+ * advances it `depth` steps per pass over memory; 2 = temporal blocking with
+ * lane-interleaved cells (consecutive cells in consecutive lanes, so table
+ * reads coalesce), split kinds only.  Zero fields mean "keep". */
 typedef struct {
   int32_t kernel;
   int32_t vec;          /* cells per lane                                                */
@@ -187,6 +189,13 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan);
 fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial);
 
 fqnm_status fqnm_destroy(fqnm_ctx* ctx); /* NULL-safe */
+
+/* Quantise a real field on the device (Sec. 2, eq:quantisation):
+ * q_host[i] = rint(u_host[i] / delta) for i < n, stored as itype.
+ * FQNM_ERR_RANGE if a value does not fit the storage type (or |q| >= 2^52
+ * for FQNM_I64).  Syncs hip_stream. */
+fqnm_status fqnm_quantise(const double* u_host, int64_t n, double delta, int32_t itype,
+                          void* q_host, void* hip_stream);
 
 /* Self-check of the FP64 operations the Euler transfer relies on: evaluates,
  * with the library's own device code generation, out_sqrt[i] = sqrt(d_a[i])

@@ -307,7 +307,7 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
   const bool lut = p.eval == FQNM_EVAL_LUT;
   if (lut) {
     const int64_t count = hi - lo + 1;
-    if (count > (int64_t(1) << 28)) return fail(FQNM_ERR_RANGE, "LUT range too large");
+    if (count >= (int64_t(1) << 28)) return fail(FQNM_ERR_RANGE, "LUT range too large");
     const size_t eb = p.itype == FQNM_I32 ? 8 : 16;
     if (hipMalloc(&ctx->d_lut, eb * count) != hipSuccess)
       return fail(FQNM_ERR_OOM, "hipMalloc of the LUT failed");
@@ -437,8 +437,8 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
                         ctx->d_ledger, ctx->stream);
     } else {
       k = std::min<int64_t>(pl.depth, left);
-      const int khalo = scalar_halo(pl.vec, static_cast<int>(k));
-      e = launch_scalar(p.itype, ctx->pol, K_TBLOCK, pl.vec, src, dst, p.n, p.bc,
+      const int khalo = scalar_halo(pl.kernel, pl.vec, static_cast<int>(k));
+      e = launch_scalar(p.itype, ctx->pol, pl.kernel, pl.vec, src, dst, p.n, p.bc,
                         static_cast<int>(k), khalo, ctx->xp, ctx->d_ledger, ctx->stream);
     }
     if (e != hipSuccess) {
@@ -546,6 +546,38 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
   return FQNM_OK;
 }
 
+fqnm_status fqnm_quantise(const double* u_host, int64_t n, double delta, int32_t itype,
+                          void* q_host, void* hip_stream) {
+  if (!u_host || !q_host || n < 0) return fail(FQNM_ERR_ARG, "NULL argument or negative n");
+  if (!(std::isfinite(delta) && delta > 0.0)) return fail(FQNM_ERR_ARG, "delta must be > 0");
+  if (itype != FQNM_I32 && itype != FQNM_I64) return fail(FQNM_ERR_ARG, "unknown itype");
+  if (n == 0) return FQNM_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t es = itype == FQNM_I32 ? 4 : 8;
+  double* du = nullptr;
+  void* dq = nullptr;
+  int* derr = nullptr;
+  fqnm_status st = FQNM_OK;
+  if (hipMalloc(&du, sizeof(double) * n) != hipSuccess || hipMalloc(&dq, es * n) != hipSuccess ||
+      hipMalloc(&derr, sizeof(int)) != hipSuccess)
+    st = fail(FQNM_ERR_OOM, "hipMalloc failed");
+  int herr = 0;
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(du, u_host, sizeof(double) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(derr, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_quantise(itype, du, dq, n, delta, derr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(q_host, dq, es * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "quantise");
+    else if (herr) st = fail(FQNM_ERR_RANGE, "u/delta exceeds the storage range");
+  }
+  if (du) (void)hipFree(du);
+  if (dq) (void)hipFree(dq);
+  if (derr) (void)hipFree(derr);
+  return st;
+}
+
 fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out) {
   if (!ctx || !out) return fail(FQNM_ERR_ARG, "NULL argument");
   *out = ctx->plan;
@@ -557,15 +589,16 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (!ctx || !plan) return fail(FQNM_ERR_ARG, "NULL argument");
   if (ctx->euler) return fail(FQNM_ERR_UNSUPPORTED, "Euler contexts have a fixed plan");
   fqnm_plan pl = ctx->plan;
-  if (plan->kernel == K_STREAM || plan->kernel == K_TBLOCK) pl.kernel = plan->kernel;
+  if (plan->kernel == K_STREAM || plan->kernel == K_TBLOCK || plan->kernel == K_TBLOCK_IL)
+    pl.kernel = plan->kernel;
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
   if (plan->depth) pl.depth = plan->depth;
   if (!scalar_variant_available(ctx->prob.itype, ctx->pol, pl.kernel, pl.vec))
     return fail(FQNM_ERR_ARG, "vec not available for this storage type");
-  if (pl.kernel == K_TBLOCK) {
+  if (pl.kernel != K_STREAM) {
     if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth must be >= 1");
-    const int kh = scalar_halo(pl.vec, pl.depth);
+    const int kh = scalar_halo(pl.kernel, pl.vec, pl.depth);
     if (64 * pl.vec - 2 * kh < pl.vec) return fail(FQNM_ERR_ARG, "depth too large for vec");
   }
   ctx->plan = pl;
@@ -596,8 +629,14 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     const int PER = i32 ? 4 : 2;
     if (v >= 2 * PER) cand.push_back({K_STREAM, v, 1, 0});
     for (int d : {4, 8, 16, 32, 64, 96}) {
-      const int kh = scalar_halo(v, d);
+      const int kh = scalar_halo(K_TBLOCK, v, d);
       if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
+    }
+    if (scalar_variant_available(ctx->prob.itype, ctx->pol, K_TBLOCK_IL, v)) {
+      for (int d : {16, 32, 64, 128}) {
+        const int kh = scalar_halo(K_TBLOCK_IL, v, d);
+        if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK_IL, v, d, 0});
+      }
     }
   }
   hipEvent_t e0, e1;

@@ -1,23 +1,460 @@
-// batch.hip -- batched execution of many independent instances (work in progress).
+// batch.hip -- many independent instances advanced by one persistent launch.
+//
+// Every instance is a scalar problem of its own (flux kind, constants, size,
+// boundary, step count).  Instances of int32 cells with n <= 512*128 run in
+// the persistent kernel below: a 512-thread workgroup takes one instance at a
+// time from a device work counter (longest first), loads all of its cells into
+// registers (V consecutive cells per lane, V chosen per instance), advances
+// them through every one of the instance's steps, and stores them once.  HBM
+// is touched twice per instance, whatever its step count.
+//
+// Per step each lane needs the cell left of its first cell and right of its
+// last one.  Inside a wavefront they arrive by cross-lane moves; across
+// wavefronts each wavefront publishes its two edge cells in LDS (double
+// buffered by step parity, one barrier per step).  With L = ceil(n/V) lanes
+// in use, the last S = L*V - n lanes hold V-1 cells, so every lane's cells
+// are contiguous, cell 0 is slot 0 of lane 0 and cell n-1 is the last real
+// slot of lane L-1: the boundary neighbours (periodic wrap or outflow copy)
+// come from fixed slots, with no data-dependent register indexing.
+//
+// Instances outside that envelope (int64 cells, larger n, tabulated maps,
+// Lax-Friedrichs kinds) are advanced by the single-grid stepper on the same
+// stream.  The whole run is captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
 
 #include "runtime.h"
 
+namespace fqnm {
+namespace {
+
+constexpr int BT = 512;            // threads of the persistent workgroup
+constexpr int BW = BT / 64;        // wavefronts per workgroup
+constexpr int BMAXV = 128;         // largest cells-per-lane variant
+constexpr int64_t BMAXN = int64_t(BT) * BMAXV;
+
+struct BInst {
+  int64_t off;     // first cell in the concatenated state array
+  int32_t n;
+  int32_t steps;
+  int32_t pol;     // P_UPWIND_POS, P_UPWIND_NEG, P_EO, P_GODUNOV, P_MURMAN_ROE
+  int32_t vec;     // cells per lane
+  int32_t bc;
+  int32_t pad_;
+  double c;        // a*lambda
+  double h;        // (delta*lambda)*0.5
+};
+
+template <int POL>
+__device__ __forceinline__ void maps32(const XParams& P, int32_t q, int32_t& pp, int32_t& pm) {
+  pp = split_phi<int32_t, POL>(P, q, true);
+  pm = split_phi<int32_t, POL>(P, q, false);
+}
+
+template <int POL, int V>
+__device__ void run_resident(const BInst& I, int32_t* __restrict__ state, int32_t* s_first,
+                             int32_t* s_last, int32_t* s_q0, int32_t* s_qn1) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = I.n;
+  const int L = (n + V - 1) / V;  // lanes in use
+  const int S = L * V - n;        // the last S lanes hold V-1 cells ("short" lanes)
+  const int wused = (L + 63) / 64;
+  const bool periodic = I.bc == FQNM_BC_PERIODIC;
+  const bool active = tid < L;
+  const bool shortl = tid >= L - S;
+  const int start = tid * V - (tid > L - S ? tid - (L - S) : 0);  // first cell of this lane
+  int32_t* st = state + I.off;
+  XParams P;
+  P.c = I.c;
+  P.h = I.h;
+  int32_t q[V];
+  if (active) {
+    // V contiguous cells; the last slot of a short lane reads its right
+    // neighbour (or the guard cells behind the instance) and is never stored
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = st[start + j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = 0;
+  }
+  for (int s = 0; s < I.steps; ++s) {
+    const int b = s & 1;
+    const int32_t mylast = shortl ? q[V - 2 >= 0 ? V - 2 : 0] : q[V - 1];
+    if (wave < wused) {
+      if (lane == 0) s_first[b * BW + wave] = q[0];
+      if (lane == 63) s_last[b * BW + wave] = mylast;
+      if (tid == 0) s_q0[b] = q[0];
+      if (tid == L - 1) s_qn1[b] = mylast;
+    }
+    __syncthreads();
+    if (wave >= wused) continue;
+    int32_t qp = __shfl_up(mylast, 1, 64);
+    int32_t qn = __shfl_down(q[0], 1, 64);
+    if (lane == 0 && wave > 0) qp = s_last[b * BW + wave - 1];
+    if (lane == 63 && wave + 1 < BW) qn = s_first[b * BW + wave + 1];
+    if (tid == 0) qp = periodic ? s_qn1[b] : q[0];      // ghost left of cell 0
+    if (tid == L - 1) qn = periodic ? s_q0[b] : mylast;  // ghost right of cell n-1
+    if constexpr (IsSplit<POL>::value) {
+      int32_t ppc, pmc, a, bb;
+      maps32<POL>(P, q[0], ppc, pmc);
+      maps32<POL>(P, qp, a, bb);
+      int32_t Fprev = a + pmc;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        int32_t nxt = j + 1 < V ? q[j + 1] : qn;
+        if (j == V - 2) nxt = shortl ? qn : nxt;
+        int32_t ppn, pmn;
+        maps32<POL>(P, nxt, ppn, pmn);
+        const int32_t F = ppc + pmn;
+        const int32_t v = wsub<int32_t>(q[j], wsub<int32_t>(F, Fprev));
+        q[j] = (j == V - 1 && shortl) ? q[j] : v;
+        Fprev = F;
+        ppc = ppn;
+      }
+    } else {
+      int32_t Fprev = transfer<int32_t, POL>(P, qp, q[0]);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        int32_t nxt = j + 1 < V ? q[j + 1] : qn;
+        if (j == V - 2) nxt = shortl ? qn : nxt;
+        const int32_t F = transfer<int32_t, POL>(P, q[j], nxt);
+        const int32_t v = wsub<int32_t>(q[j], wsub<int32_t>(F, Fprev));
+        q[j] = (j == V - 1 && shortl) ? q[j] : v;
+        Fprev = F;
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (j < V - 1 || !shortl) st[start + j] = q[j];
+  }
+}
+
+template <int POL>
+__device__ void run_by_vec(const BInst& I, int32_t* state, int32_t* a, int32_t* b, int32_t* c,
+                           int32_t* d) {
+  switch (I.vec) {
+    case 2: run_resident<POL, 2>(I, state, a, b, c, d); break;
+    case 4: run_resident<POL, 4>(I, state, a, b, c, d); break;
+    case 8: run_resident<POL, 8>(I, state, a, b, c, d); break;
+    case 16: run_resident<POL, 16>(I, state, a, b, c, d); break;
+    case 32: run_resident<POL, 32>(I, state, a, b, c, d); break;
+    case 64: run_resident<POL, 64>(I, state, a, b, c, d); break;
+    default:
+      // the widest variant keeps 128 cells per lane in registers; it is built
+      // for the split kinds only (two-point kinds need more temporaries and
+      // stop at 64, their larger instances use the single-grid stepper)
+      if constexpr (IsSplit<POL>::value) run_resident<POL, 128>(I, state, a, b, c, d);
+      break;
+  }
+}
+
+__global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__ insts,
+                                                       const int32_t* __restrict__ order,
+                                                       int32_t count, int32_t* counter,
+                                                       int32_t* __restrict__ state) {
+  __shared__ int32_t s_first[2 * BW], s_last[2 * BW], s_q0[2], s_qn1[2];
+  __shared__ int32_t s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int32_t k = s_next;
+    __syncthreads();
+    if (k >= count) return;  // every workgroup leaves once the counter passes the end
+    const BInst I = insts[order[k]];
+    switch (I.pol) {
+      case P_UPWIND_POS: run_by_vec<P_UPWIND_POS>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_UPWIND_NEG: run_by_vec<P_UPWIND_NEG>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_EO: run_by_vec<P_EO>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_GODUNOV: run_by_vec<P_GODUNOV>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      default: run_by_vec<P_MURMAN_ROE>(I, state, s_first, s_last, s_q0, s_qn1); break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_counter(int32_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+bool resident_policy(int pol) {
+  return pol == P_UPWIND_POS || pol == P_UPWIND_NEG || pol == P_EO || pol == P_GODUNOV ||
+         pol == P_MURMAN_ROE;
+}
+
+// cells per lane for an instance of n cells with at most `lanes` lanes in use
+int pick_vec(int64_t n, int lanes) {
+  for (int v = 2; v <= BMAXV; v *= 2)
+    if ((n + v - 1) / v <= lanes) return v;
+  return BMAXV;
+}
+
+int64_t resident_max_n(int pol) {
+  return (pol == P_GODUNOV || pol == P_MURMAN_ROE) ? int64_t(BT) * 64 : BMAXN;
+}
+
+}  // namespace
+}  // namespace fqnm
+
 using namespace fqnm;
 
+struct fqnm_batch {
+  hipStream_t user = nullptr;
+  hipStream_t stream = nullptr;  // the library's capture/launch stream
+  int32_t count = 0;
+  std::vector<fqnm_problem> probs;
+  std::vector<int64_t> steps;
+  std::vector<int64_t> off;      // element offset of each instance
+  std::vector<int> resident;     // 1 if run by the persistent kernel
+  int64_t total = 0;             // elements
+  void* d_state = nullptr;
+  void* d_init = nullptr;
+  BInst* d_insts = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_counter = nullptr;
+  int32_t n_resident = 0;
+  int grid = 0;
+  int lanes = BT;
+  std::vector<fqnm_ctx*> big;    // fallback single-grid contexts (borrowing their slices)
+  std::vector<int64_t> big_steps;
+  std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool poisoned = false;
+};
+
+static size_t esize_of(const fqnm_problem& p) { return p.itype == FQNM_I32 ? 4 : 8; }
+
+static void batch_free(fqnm_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto* c : b->big) fqnm_destroy(c);
+  for (auto* c : b->solo) fqnm_destroy(c);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_state) (void)hipFree(b->d_state);
+  if (b->d_init) (void)hipFree(b->d_init);
+  if (b->d_insts) (void)hipFree(b->d_insts);
+  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+#define B_HIP(call, what)              \
+  do {                                 \
+    hipError_t e_ = (call);            \
+    if (e_ != hipSuccess) {            \
+      b->poisoned = true;              \
+      return hip_fail(e_, what);       \
+    }                                  \
+  } while (0)
+
+static fqnm_status batch_build_graph(fqnm_batch* b) {
+  B_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t e = hipSuccess;
+  fqnm_status st = FQNM_OK;
+  if (b->n_resident > 0) {
+    k_zero_counter<<<1, 64, 0, b->stream>>>(b->d_counter);
+    k_batch_resident<<<dim3(b->grid), dim3(BT), 0, b->stream>>>(
+        b->d_insts, b->d_order, b->n_resident, b->d_counter, static_cast<int32_t*>(b->d_state));
+    e = hipGetLastError();
+  }
+  for (size_t i = 0; i < b->big.size() && e == hipSuccess && st == FQNM_OK; ++i)
+    st = fqnm_step(b->big[i], b->big_steps[i]);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); b->poisoned = true; return hip_fail(e, "batch launch"); }
+  if (st) { if (g) (void)hipGraphDestroy(g); b->poisoned = true; return st; }
+  if (e2 != hipSuccess) { b->poisoned = true; return hip_fail(e2, "end capture"); }
+  b->graph = g;
+  B_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  return FQNM_OK;
+}
+
 extern "C" {
-fqnm_status fqnm_batch_create(const fqnm_problem*, const void* const*, const int64_t*, int32_t,
-                              void*, fqnm_batch** out) {
-  if (out) *out = nullptr;
-  return fail(FQNM_ERR_UNSUPPORTED, "batching is not built yet");
+
+fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
+                              const int64_t* steps, int32_t count, void* hip_stream,
+                              fqnm_batch** out) {
+  if (!out) return fail(FQNM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!probs || !q0s || !steps || count < 1) return fail(FQNM_ERR_ARG, "empty or NULL batch");
+  fqnm_batch* b = new fqnm_batch();
+  b->user = static_cast<hipStream_t>(hip_stream);
+  b->count = count;
+  b->probs.assign(probs, probs + count);
+  b->steps.assign(steps, steps + count);
+  std::vector<BInst> host_insts;
+  std::vector<int32_t> res_ids;
+  // validate and lay out: every instance starts on a 16-byte boundary
+  for (int32_t k = 0; k < count; ++k) {
+    const fqnm_problem& p = probs[k];
+    fqnm_status st = validate_problem(&p);
+    if (st == FQNM_OK && is_euler(p.flux)) st = fail(FQNM_ERR_ARG, "batches take scalar kinds");
+    if (st == FQNM_OK && (steps[k] < 0 || !q0s[k])) st = fail(FQNM_ERR_ARG, "bad steps or q0");
+    if (st == FQNM_OK && p.itype != probs[0].itype)
+      st = fail(FQNM_ERR_ARG, "all instances of a batch share one itype");
+    if (st) { batch_free(b); return st; }
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t i = 0; i < p.n; ++i) {
+      const int64_t v = p.itype == FQNM_I32 ? static_cast<const int32_t*>(q0s[k])[i]
+                                            : static_cast<const int64_t*>(q0s[k])[i];
+      lo = std::min(lo, v);
+      hi = std::max(hi, v);
+    }
+    st = validate_range(p, lo, hi);
+    if (st) { batch_free(b); return st; }
+    const int64_t per16 = 16 / esize_of(p);
+    b->off.push_back(b->total);
+    b->total += (p.n + 1 + per16 - 1) / per16 * per16;  // at least one guard cell behind
+    const int pol = policy_of(p, false);
+    const bool res = p.itype == FQNM_I32 && p.n <= resident_max_n(pol) &&
+                     p.eval != FQNM_EVAL_LUT &&
+                     resident_policy(pol) && steps[k] <= INT32_MAX;
+    b->resident.push_back(res ? 1 : 0);
+    if (res) {
+      BInst I;
+      std::memset(&I, 0, sizeof I);
+      I.off = b->off.back();
+      I.n = static_cast<int32_t>(p.n);
+      I.steps = static_cast<int32_t>(steps[k]);
+      I.pol = pol;
+      I.vec = pick_vec(p.n, b->lanes);
+      I.bc = p.bc;
+      XParams x = xparams_of(p);
+      I.c = x.c;
+      I.h = x.h;
+      res_ids.push_back(static_cast<int32_t>(host_insts.size()));
+      host_insts.push_back(I);
+    }
+  }
+  const size_t es = esize_of(probs[0]);
+  fqnm_status st = FQNM_OK;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+    st = fail(FQNM_ERR_DEVICE, "stream/event creation failed");
+  if (!st && (hipMalloc(&b->d_state, es * b->total) != hipSuccess ||
+              hipMalloc(&b->d_init, es * b->total) != hipSuccess ||
+              hipMalloc(&b->d_counter, sizeof(int32_t)) != hipSuccess))
+    st = fail(FQNM_ERR_OOM, "batch state allocation failed");
+  for (int32_t k = 0; k < count && !st; ++k) {
+    if (hipMemcpyAsync(static_cast<char*>(b->d_init) + es * b->off[k], q0s[k],
+                       es * probs[k].n, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      st = fail(FQNM_ERR_DEVICE, "copy q0");
+  }
+  if (!st && hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice,
+                            b->stream) != hipSuccess)
+    st = fail(FQNM_ERR_DEVICE, "copy state");
+  b->n_resident = static_cast<int32_t>(host_insts.size());
+  if (!st && b->n_resident > 0) {
+    // longest work first
+    std::vector<int32_t> order(b->n_resident);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return int64_t(host_insts[x].n) * host_insts[x].steps >
+             int64_t(host_insts[y].n) * host_insts[y].steps;
+    });
+    if (hipMalloc(&b->d_insts, sizeof(BInst) * host_insts.size()) != hipSuccess ||
+        hipMalloc(&b->d_order, sizeof(int32_t) * order.size()) != hipSuccess)
+      st = fail(FQNM_ERR_OOM, "batch table allocation failed");
+    if (!st && (hipMemcpyAsync(b->d_insts, host_insts.data(), sizeof(BInst) * host_insts.size(),
+                               hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+                hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
+                               hipMemcpyHostToDevice, b->stream) != hipSuccess))
+      st = fail(FQNM_ERR_DEVICE, "copy batch table");
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident, BT, 0) !=
+            hipSuccess || per_cu < 1)
+      per_cu = 1;
+    b->grid = std::max(1, std::min<int>(cus * per_cu, b->n_resident));
+  }
+  // instances outside the resident envelope: single-grid contexts on their slices
+  for (int32_t k = 0; k < count && !st; ++k) {
+    if (b->resident[k]) continue;
+    fqnm_ctx* c = nullptr;
+    st = fqnm_create_on_device(&probs[k], static_cast<char*>(b->d_state) + es * b->off[k],
+                               b->stream, &c);
+    if (!st) {
+      b->big.push_back(c);
+      b->big_steps.push_back(steps[k]);
+    }
+  }
+  if (!st && hipStreamSynchronize(b->stream) != hipSuccess)
+    st = fail(FQNM_ERR_DEVICE, "batch setup sync");
+  if (!st) st = batch_build_graph(b);
+  if (st) { batch_free(b); return st; }
+  *out = b;
+  return FQNM_OK;
 }
-fqnm_status fqnm_batch_reset(fqnm_batch*) { return fail(FQNM_ERR_UNSUPPORTED, "no batch"); }
-fqnm_status fqnm_batch_run(fqnm_batch*) { return fail(FQNM_ERR_UNSUPPORTED, "no batch"); }
-fqnm_status fqnm_batch_run_per_instance(fqnm_batch*) {
-  return fail(FQNM_ERR_UNSUPPORTED, "no batch");
+
+fqnm_status fqnm_batch_reset(fqnm_batch* b) {
+  if (!b) return fail(FQNM_ERR_ARG, "batch is NULL");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  const size_t es = esize_of(b->probs[0]);
+  B_HIP(hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice, b->user),
+        "reset");
+  return FQNM_OK;
 }
-fqnm_status fqnm_batch_get_state(fqnm_batch*, int32_t, void*) {
-  return fail(FQNM_ERR_UNSUPPORTED, "no batch");
+
+fqnm_status fqnm_batch_run(fqnm_batch* b) {
+  if (!b) return fail(FQNM_ERR_ARG, "batch is NULL");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  B_HIP(hipEventRecord(b->ev_in, b->user), "record");
+  B_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0), "wait");
+  B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
+  B_HIP(hipEventRecord(b->ev_out, b->stream), "record");
+  B_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0), "wait");
+  return FQNM_OK;
 }
-fqnm_status fqnm_batch_destroy(fqnm_batch*) { return FQNM_OK; }
+
+fqnm_status fqnm_batch_run_per_instance(fqnm_batch* b) {
+  if (!b) return fail(FQNM_ERR_ARG, "batch is NULL");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  const size_t es = esize_of(b->probs[0]);
+  if (b->solo.empty()) {
+    for (int32_t k = 0; k < b->count; ++k) {
+      fqnm_ctx* c = nullptr;
+      fqnm_status st = fqnm_create_on_device(&b->probs[k],
+                                             static_cast<char*>(b->d_state) + es * b->off[k],
+                                             b->user, &c);
+      if (st) return st;
+      b->solo.push_back(c);
+    }
+  }
+  for (int32_t k = 0; k < b->count; ++k) {
+    fqnm_status st = fqnm_step(b->solo[k], b->steps[k]);
+    if (st) return st;
+  }
+  return FQNM_OK;
 }
+
+fqnm_status fqnm_batch_get_state(fqnm_batch* b, int32_t idx, void* q_host) {
+  if (!b || !q_host) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (idx < 0 || idx >= b->count) return fail(FQNM_ERR_ARG, "index out of range");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  const size_t es = esize_of(b->probs[idx]);
+  B_HIP(hipStreamSynchronize(b->stream), "sync");
+  B_HIP(hipMemcpyAsync(q_host, static_cast<char*>(b->d_state) + es * b->off[idx],
+                       es * b->probs[idx].n, hipMemcpyDeviceToHost, b->user), "copy state");
+  B_HIP(hipStreamSynchronize(b->user), "sync");
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_batch_destroy(fqnm_batch* b) {
+  batch_free(b);
+  return FQNM_OK;
+}
+
+}  // extern "C"

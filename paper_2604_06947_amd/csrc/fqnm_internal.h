@@ -12,7 +12,7 @@
 
 namespace fqnm {
 
-enum : int { K_STREAM = 0, K_TBLOCK = 1 };
+enum : int { K_STREAM = 0, K_TBLOCK = 1, K_TBLOCK_IL = 2 };
 
 // Per-block partial results of the reduction kernel (one record per block).
 struct ReducePartial {
@@ -31,7 +31,7 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
                          int64_t n, int bc, int ksteps, int khalo, const XParams& P,
                          long long* d_ledger, hipStream_t s);
 bool scalar_variant_available(int itype, int pol, int kernel, int vec);
-int scalar_halo(int vec, int ksteps);  // halo width used by K_TBLOCK
+int scalar_halo(int kernel, int vec, int ksteps);  // halo width of the temporal-blocking kernels
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
                             int64_t count, hipStream_t s);

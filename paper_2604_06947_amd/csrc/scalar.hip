@@ -67,6 +67,48 @@ __device__ __forceinline__ int64_t ghost_index(int64_t g, int64_t n, int bc) {
   return bc == FQNM_BC_PERIODIC ? wrap_index(g, n) : clamp_index(g, n);
 }
 
+// Split maps of one cell: {phi+(q), phi-(q)}; a single 8- or 16-byte table
+// read in LUT mode.  For int32 states the read is a raw buffer load whose
+// resource holds the table size, so the hardware range check returns zeros
+// for any offset past the table instead of touching other memory; states of
+// cells inside the domain never leave [lo, hi] (maximum principle), so only
+// discarded halo lanes can ever be out of range.
+struct LutView {
+  __amdgpu_buffer_rsrc_t rsrc;
+};
+
+__device__ __forceinline__ LutView lut_view(const XParams& P) {
+  LutView v;
+  const int64_t bytes = (P.lut_last + 1) * 8;
+  v.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(P.lut), static_cast<short>(0),
+                                             static_cast<int>(bytes), 0x00020000);
+  return v;
+}
+
+template <typename IT, int POL>
+__device__ __forceinline__ void cell_maps(const XParams& P, const LutView& L, IT q, IT& pp,
+                                          IT& pm) {
+  if constexpr (POL == P_LUT) {
+    if constexpr (sizeof(IT) == 4) {
+      const uint32_t off = (static_cast<uint32_t>(q) - static_cast<uint32_t>(P.lut_lo)) << 3;
+      const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
+      pp = static_cast<IT>(e[0]);
+      pm = static_cast<IT>(e[1]);
+    } else {
+      using E = typename LutEntry<IT>::T;
+      uint64_t i = static_cast<uint64_t>(q) - static_cast<uint64_t>(P.lut_lo);
+      const uint64_t last = static_cast<uint64_t>(P.lut_last);
+      i = i < last ? i : last;  // clamped: never outside the table
+      const E e = static_cast<const E*>(P.lut)[i];
+      pp = static_cast<IT>(e.x);
+      pm = static_cast<IT>(e.y);
+    }
+  } else {
+    pp = split_phi<IT, POL>(P, q, true);
+    pm = split_phi<IT, POL>(P, q, false);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K1: one step per pass.
 // ---------------------------------------------------------------------------
@@ -85,13 +127,35 @@ __global__ __launch_bounds__(256) void k_stream(const IT* __restrict__ src, IT* 
 #pragma unroll
     for (int j = 0; j < V; ++j) q[j] = src[ghost_index(base + j, n, bc)];
   }
-  IT qn = lane_from_next<IT>(q[0]);
-  if (lane == 63) qn = src[ghost_index(base + V, n, bc)];
   IT F[V];
+  IT Fl;
+  if constexpr (IsSplit<POL>::value) {
+    const LutView L = lut_view(P);
+    IT pp[V], pm[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) F[j] = transfer<IT, POL>(P, q[j], j + 1 < V ? q[j + 1] : qn);
-  IT Fl = lane_from_prev<IT>(F[V - 1]);
-  if (lane == 0) Fl = transfer<IT, POL>(P, src[ghost_index(base - 1, n, bc)], q[0]);
+    for (int j = 0; j < V; ++j) cell_maps<IT, POL>(P, L, q[j], pp[j], pm[j]);
+    IT pmn = lane_from_next<IT>(pm[0]);
+    if (lane == 63) {
+      IT a, b;
+      cell_maps<IT, POL>(P, L, src[ghost_index(base + V, n, bc)], a, b);
+      pmn = b;
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) F[j] = pp[j] + (j + 1 < V ? pm[j + 1] : pmn);
+    Fl = lane_from_prev<IT>(F[V - 1]);
+    if (lane == 0) {
+      IT a, b;
+      cell_maps<IT, POL>(P, L, src[ghost_index(base - 1, n, bc)], a, b);
+      Fl = a + pm[0];
+    }
+  } else {
+    IT qn = lane_from_next<IT>(q[0]);
+    if (lane == 63) qn = src[ghost_index(base + V, n, bc)];
+#pragma unroll
+    for (int j = 0; j < V; ++j) F[j] = transfer<IT, POL>(P, q[j], j + 1 < V ? q[j + 1] : qn);
+    Fl = lane_from_prev<IT>(F[V - 1]);
+    if (lane == 0) Fl = transfer<IT, POL>(P, src[ghost_index(base - 1, n, bc)], q[0]);
+  }
   IT out[V];
   out[0] = wsub<IT>(q[0], wsub<IT>(F[0], Fl));
 #pragma unroll
@@ -117,44 +181,67 @@ __global__ __launch_bounds__(256) void k_stream(const IT* __restrict__ src, IT* 
 }
 
 // ---------------------------------------------------------------------------
-// K2: temporal blocking in registers.
+// K2: temporal blocking in registers, lane-contiguous cells.
 // ---------------------------------------------------------------------------
-template <typename IT, int POL, int V>
-__device__ __forceinline__ void tb_step_plain(const XParams& P, IT (&q)[V]) {
-  IT qn = lane_from_next<IT>(q[0]);
+// Interface fluxes of one step for the cells q[0..V) of every lane; the last
+// interface of a lane needs the next lane's first cell, the first cell's left
+// interface arrives from the previous lane.  With `edge` the outflow rules of
+// the domain ends apply at global positions g0+j (frozen outside [0, n)).
+template <typename IT, int POL, int V, bool EDGE>
+__device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, IT (&q)[V],
+                                        int64_t g0, int64_t n, bool own_right, long long& led) {
   IT F[V];
+  if constexpr (IsSplit<POL>::value) {
+    IT pp[V], pm[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) F[j] = transfer<IT, POL>(P, q[j], j + 1 < V ? q[j + 1] : qn);
-  IT Fl = lane_from_prev<IT>(F[V - 1]);
-  q[0] = wsub<IT>(q[0], wsub<IT>(F[0], Fl));
+    for (int j = 0; j < V; ++j) cell_maps<IT, POL>(P, L, q[j], pp[j], pm[j]);
+    const IT pmn = lane_from_next<IT>(pm[0]);
+    if constexpr (!EDGE) {
 #pragma unroll
-  for (int j = 1; j < V; ++j) q[j] = wsub<IT>(q[j], wsub<IT>(F[j], F[j - 1]));
-}
-
-// Outflow tile touching a domain end: boundary interfaces use the in-domain
-// cell on both sides, positions outside [0, n) stay frozen.
-template <typename IT, int POL, int V>
-__device__ __forceinline__ void tb_step_outflow(const XParams& P, IT (&q)[V], int64_t g0,
-                                                int64_t n, bool own_right, long long& led) {
-  IT qn = lane_from_next<IT>(q[0]);
-  IT F[V];
+      for (int j = 0; j < V; ++j) F[j] = pp[j] + (j + 1 < V ? pm[j + 1] : pmn);
+    } else {
+      const IT ppn = lane_from_next<IT>(pp[0]);
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const int64_t g = g0 + j;
-    IT qL = q[j];
-    IT qR = j + 1 < V ? q[j + 1] : qn;
-    if (g == -1) qL = qR;
-    if (g == n - 1) qR = qL;
-    F[j] = transfer<IT, POL>(P, qL, qR);
-    if (g == -1) led += static_cast<long long>(F[j]);
-    if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
+      for (int j = 0; j < V; ++j) {
+        const int64_t g = g0 + j;
+        const IT ppR = j + 1 < V ? pp[j + 1] : ppn;
+        const IT pmR = j + 1 < V ? pm[j + 1] : pmn;
+        IT f = pp[j] + pmR;
+        if (g == -1) f = ppR + pmR;        // F_{-1/2} = T(q_0, q_0)
+        if (g == n - 1) f = pp[j] + pm[j]; // F_{n-1/2} = T(q_{n-1}, q_{n-1})
+        F[j] = f;
+        if (g == -1) led += static_cast<long long>(f);
+        if (g == n - 1 && own_right) led -= static_cast<long long>(f);
+      }
+    }
+  } else {
+    const IT qn = lane_from_next<IT>(q[0]);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      IT qL = q[j];
+      IT qR = j + 1 < V ? q[j + 1] : qn;
+      if constexpr (EDGE) {
+        const int64_t g = g0 + j;
+        if (g == -1) qL = qR;
+        if (g == n - 1) qR = qL;
+        F[j] = transfer<IT, POL>(P, qL, qR);
+        if (g == -1) led += static_cast<long long>(F[j]);
+        if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
+      } else {
+        F[j] = transfer<IT, POL>(P, qL, qR);
+      }
+    }
   }
-  IT Fl = lane_from_prev<IT>(F[V - 1]);
+  const IT Fl = lane_from_prev<IT>(F[V - 1]);
 #pragma unroll
   for (int j = 0; j < V; ++j) {
-    const int64_t g = g0 + j;
-    IT d = wsub<IT>(F[j], j == 0 ? Fl : F[j - 1]);
-    if (g >= 0 && g < n) q[j] = wsub<IT>(q[j], d);
+    const IT d = wsub<IT>(F[j], j == 0 ? Fl : F[j - 1]);
+    if constexpr (EDGE) {
+      const int64_t g = g0 + j;
+      if (g >= 0 && g < n) q[j] = wsub<IT>(q[j], d);
+    } else {
+      q[j] = wsub<IT>(q[j], d);
+    }
   }
 }
 
@@ -180,11 +267,12 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
     for (int j = 0; j < V; ++j) q[j] = src[ghost_index(g0 + j, n, bc)];
   }
   long long led = 0;
+  const LutView L = lut_view(P);
   if (inside || bc == FQNM_BC_PERIODIC) {
-    for (int s = 0; s < ksteps; ++s) tb_step_plain<IT, POL, V>(P, q);
+    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, q, g0, n, false, led);
   } else {
     const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
-    for (int s = 0; s < ksteps; ++s) tb_step_outflow<IT, POL, V>(P, q, g0, n, own_right, led);
+    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, q, g0, n, own_right, led);
   }
   const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;
   if (lane >= lane_lo && lane < lane_hi) {
@@ -195,6 +283,124 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
       for (int j = 0; j < V; ++j)
         if (g0 + j < n) dst[g0 + j] = q[j];
     }
+  }
+  if (led != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
+}
+
+// ---------------------------------------------------------------------------
+// K3: temporal blocking in registers, lane-interleaved cells (split kinds).
+// Position p = j*64 + lane of the wavefront tile holds slot j of that lane, so
+// a table read of slot j touches the maps of 64 consecutive cells (a few cache
+// lines) instead of 64 cells spread V apart.  Every neighbour is one lane
+// away: values move by a rotation of the wavefront (ds_bpermute), and the
+// lane at the end of a slot takes the value rotated out of the adjacent slot.
+// The halo is a whole number of slots (khalo % 64 == 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+
+template <typename IT>
+__device__ __forceinline__ IT rotate(int addr, IT v) {
+  if constexpr (sizeof(IT) == 4) {
+    return static_cast<IT>(bperm(addr, static_cast<int>(v)));
+  } else {
+    const uint64_t u = static_cast<uint64_t>(v);
+    const int lo = bperm(addr, static_cast<int>(static_cast<uint32_t>(u)));
+    const int hi = bperm(addr, static_cast<int>(static_cast<uint32_t>(u >> 32)));
+    return static_cast<IT>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                           static_cast<uint32_t>(lo));
+  }
+}
+
+template <typename IT, int POL, int V, bool EDGE>
+__device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (&q)[V], int lane,
+                                        int a_next,
+                                        int a_prev, int64_t wstart, int64_t n, bool own_right,
+                                        long long& led) {
+  IT pp[V], pm[V], F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) cell_maps<IT, POL>(P, L, q[j], pp[j], pm[j]);
+  // pm of the right neighbour: lane l+1 of the same slot, or lane 0 of slot j+1
+  IT rm[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) rm[j] = rotate<IT>(a_next, pm[j]);
+  if constexpr (!EDGE) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const IT pmR = (lane == 63 && j + 1 < V) ? rm[j + 1] : rm[j];
+      F[j] = pp[j] + pmR;
+    }
+  } else {
+    IT rp[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) rp[j] = rotate<IT>(a_next, pp[j]);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int64_t g = wstart + j * 64 + lane;
+      const IT pmR = (lane == 63 && j + 1 < V) ? rm[j + 1] : rm[j];
+      const IT ppR = (lane == 63 && j + 1 < V) ? rp[j + 1] : rp[j];
+      IT f = pp[j] + pmR;
+      if (g == -1) f = ppR + pmR;
+      if (g == n - 1) f = pp[j] + pm[j];
+      F[j] = f;
+      if (g == -1) led += static_cast<long long>(f);
+      if (g == n - 1 && own_right) led -= static_cast<long long>(f);
+    }
+  }
+  // F of the left interface: lane l-1 of the same slot, or lane 63 of slot j-1
+  IT rf[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) rf[j] = rotate<IT>(a_prev, F[j]);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const IT Fl = (lane == 0 && j > 0) ? rf[j - 1] : rf[j];
+    const IT d = wsub<IT>(F[j], Fl);
+    if constexpr (EDGE) {
+      const int64_t g = wstart + j * 64 + lane;
+      if (g >= 0 && g < n) q[j] = wsub<IT>(q[j], d);
+    } else {
+      q[j] = wsub<IT>(q[j], d);
+    }
+  }
+}
+
+template <typename IT, int POL, int V>
+__global__ __launch_bounds__(256) void k_tblock_il(const IT* __restrict__ src,
+                                                   IT* __restrict__ dst, int64_t n, int bc,
+                                                   int ksteps, int khalo, int64_t ntiles,
+                                                   XParams P, long long* __restrict__ ledger) {
+  static_assert(IsSplit<POL>::value, "interleaved tiles serve split kinds");
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= ntiles) return;
+  const int64_t T = 64 * V - 2 * khalo;
+  const int64_t tstart = tile * T;
+  const int64_t wstart = tstart - khalo;
+  const bool inside = wstart >= 0 && wstart + 64 * V <= n;
+  IT q[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int64_t g = wstart + j * 64 + lane;
+    q[j] = src[inside ? g : ghost_index(g, n, bc)];
+  }
+  const int a_next = ((lane + 1) & 63) << 2;
+  const int a_prev = ((lane + 63) & 63) << 2;
+  const LutView L = lut_view(P);
+  long long led = 0;
+  if (inside || bc == FQNM_BC_PERIODIC) {
+    for (int s = 0; s < ksteps; ++s)
+      il_step<IT, POL, V, false>(P, L, q, lane, a_next, a_prev, wstart, n, false, led);
+  } else {
+    const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
+    for (int s = 0; s < ksteps; ++s)
+      il_step<IT, POL, V, true>(P, L, q, lane, a_next, a_prev, wstart, n, own_right, led);
+  }
+  const int jlo = khalo / 64, jhi = V - khalo / 64;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int64_t g = wstart + j * 64 + lane;
+    if (j >= jlo && j < jhi && g < n) dst[g] = q[j];
   }
   if (led != 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
@@ -316,8 +522,17 @@ hipError_t do_launch(int kernel, const void* src, void* dst, int64_t n, int bc, 
     const int64_t T = 64 * V - 2 * khalo;
     const int64_t ntiles = (n + T - 1) / T;
     const int64_t blocks = (ntiles + 3) / 4;
-    k_tblock<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, b, n, bc, ksteps, khalo,
-                                                                       ntiles, P, d_ledger);
+    if (kernel == K_TBLOCK) {
+      k_tblock<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, b, n, bc, ksteps,
+                                                                         khalo, ntiles, P, d_ledger);
+    } else {
+      if constexpr (IsSplit<POL>::value) {
+        k_tblock_il<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
+            a, b, n, bc, ksteps, khalo, ntiles, P, d_ledger);
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
   }
   return hipGetLastError();
 }
@@ -371,15 +586,18 @@ unsigned grid_for(int64_t n, int threads) {
 }  // namespace
 
 bool scalar_variant_available(int itype, int pol, int kernel, int vec) {
-  if (pol < 0 || pol >= P_COUNT || (kernel != K_STREAM && kernel != K_TBLOCK)) return false;
+  if (pol < 0 || pol >= P_COUNT) return false;
+  if (kernel != K_STREAM && kernel != K_TBLOCK && kernel != K_TBLOCK_IL) return false;
+  if (kernel == K_TBLOCK_IL && (pol == P_GODUNOV || pol == P_MURMAN_ROE)) return false;
   if (itype == FQNM_I32) return vec == 4 || vec == 8 || vec == 16;
   if (itype == FQNM_I64) return vec == 2 || vec == 4 || vec == 8;
   return false;
 }
 
-int scalar_halo(int vec, int ksteps) {
-  // smallest multiple of vec that is >= ksteps (whole halo lanes)
-  return ((ksteps + vec - 1) / vec) * vec;
+int scalar_halo(int kernel, int vec, int ksteps) {
+  // whole halo lanes (lane-contiguous tiles) or whole halo slots (interleaved)
+  const int unit = kernel == K_TBLOCK_IL ? 64 : vec;
+  return ((ksteps + unit - 1) / unit) * unit;
 }
 
 hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* src, void* dst,
@@ -388,6 +606,8 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
   if (!scalar_variant_available(itype, pol, kernel, vec)) return hipErrorInvalidValue;
   if (kernel == K_STREAM && ksteps != 1) return hipErrorInvalidValue;
   if (kernel == K_TBLOCK && (khalo < ksteps || khalo % vec != 0 || 64 * vec - 2 * khalo <= 0))
+    return hipErrorInvalidValue;
+  if (kernel == K_TBLOCK_IL && (khalo < ksteps || khalo % 64 != 0 || 64 * vec - 2 * khalo <= 0))
     return hipErrorInvalidValue;
   if (itype == FQNM_I32)
     return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);

@@ -30,7 +30,7 @@ FLUX_EULER_ROE, FLUX_EULER_ROE_EF, FLUX_BURGERS_MURMAN_ROE = 5, 6, 7
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 I32, I64 = 0, 1
 EVAL_AUTO, EVAL_DIRECT, EVAL_LUT = 0, 1, 2
-KERNEL_STREAM, KERNEL_TBLOCK = 0, 1
+KERNEL_STREAM, KERNEL_TBLOCK, KERNEL_TBLOCK_IL = 0, 1, 2
 
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",
@@ -38,7 +38,7 @@ EXPORTED = [
     "fqnm_reconstruct", "fqnm_reconstruct_device", "fqnm_invariants_get", "fqnm_get_plan",
     "fqnm_set_plan", "fqnm_autotune", "fqnm_destroy", "fqnm_batch_create", "fqnm_batch_reset",
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
-    "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
+    "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
     "fqnm_server_drain", "fqnm_server_stats_get", "fqnm_server_now", "fqnm_server_destroy",
 ]
 
@@ -125,6 +125,7 @@ def lib():
             "fqnm_server_stats_get": ([vp, C.POINTER(fqnm_server_stats)], C.c_int),
             "fqnm_server_now": ([], C.c_double),
             "fqnm_fp64_selfcheck": ([vp, vp, vp, vp, i64, vp], C.c_int),
+            "fqnm_quantise": ([vp, i64, C.c_double, i32, vp, vp], C.c_int),
             "fqnm_server_destroy": ([vp], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -244,6 +245,15 @@ def fqnm_autotune(h, steps_per_trial):
 
 def fqnm_destroy(h):
     _check(lib().fqnm_destroy(h))
+
+
+def fqnm_quantise(u, delta, itype, stream=None):
+    """eq:quantisation on the device: rint(u / delta) as int32 or int64."""
+    u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+    out = np.empty(u.size, dtype=np.int32 if itype == I32 else np.int64)
+    _check(lib().fqnm_quantise(u.ctypes.data, u.size, float(delta), int(itype), out.ctypes.data,
+                               stream))
+    return out
 
 
 def fqnm_fp64_selfcheck(d_a: int, d_b: int, d_sqrt: int, d_div: int, n: int, stream=None):

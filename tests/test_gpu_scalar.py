@@ -21,9 +21,12 @@ KIND_F2O = {F.FLUX_UPWIND: O.UPWIND, F.FLUX_BURGERS_EO: O.BURGERS_EO,
 
 PLANS32 = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_STREAM, 16, 1),
            (F.KERNEL_TBLOCK, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 8, 8),
-           (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96)]
+           (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96),
+           (F.KERNEL_TBLOCK_IL, 4, 16), (F.KERNEL_TBLOCK_IL, 8, 64), (F.KERNEL_TBLOCK_IL, 16, 100)]
 PLANS64 = [(F.KERNEL_STREAM, 2, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_TBLOCK, 2, 2),
-           (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48)]
+           (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48),
+           (F.KERNEL_TBLOCK_IL, 4, 8), (F.KERNEL_TBLOCK_IL, 8, 64)]
+TWO_POINT = (F.FLUX_BURGERS_GODUNOV, F.FLUX_BURGERS_MURMAN_ROE)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -52,8 +55,11 @@ def oracle_problem(prob):
                      gamma=prob.gamma)
 
 
-def plans_for(itype):
-    return PLANS32 if itype == F.I32 else PLANS64
+def plans_for(itype, flux=None):
+    plans = PLANS32 if itype == F.I32 else PLANS64
+    if flux in TWO_POINT:  # interleaved tiles serve split kinds only
+        plans = [p for p in plans if p[0] != F.KERNEL_TBLOCK_IL]
+    return plans
 
 
 # ---------------------------------------------------------------------------
@@ -98,7 +104,7 @@ def test_kind_parity_all_plans(flux, a, lut, bc, itype):
     op = oracle_problem(prob)
     q0 = O.quantise(u0, prob.delta, op.width)
     ref, led = O.step(op, q0, steps, return_ledger=True)
-    for plan in plans_for(itype):
+    for plan in plans_for(itype, flux):
         q, inv = gpu_run(prob, u0=u0, steps=steps, plan=plan)
         assert np.array_equal(q, ref), plan
         assert inv["ledger"][0] == led
@@ -114,8 +120,10 @@ def test_edge_sizes(n, bc):
         q0 = O.quantise(u0, prob.delta, 32)
         for steps in (0, 1, 37):
             ref = O.step(op, q0, steps)
-            for plan in [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_TBLOCK, 4, 4),
-                         (F.KERNEL_TBLOCK, 16, 32)]:
+            plans = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 16, 32)]
+            if flux not in TWO_POINT:
+                plans.append((F.KERNEL_TBLOCK_IL, 4, 16))
+            for plan in plans:
                 q, _ = gpu_run(prob, q0=q0.astype(np.int32), steps=steps, plan=plan)
                 assert np.array_equal(q, ref), (flux, steps, plan)
 
@@ -199,6 +207,17 @@ def test_autotune_then_parity():
     assert np.array_equal(q, ref)
 
 
+def test_interleaved_plan_rejected_for_two_point_kinds():
+    u0, prob = make_case(F.FLUX_BURGERS_GODUNOV, F.BC_PERIODIC, F.I32, 1000, seed=1)
+    h = F.fqnm_create_from_field(prob, u0)
+    try:
+        with pytest.raises(F.FqnmError) as e:
+            F.fqnm_set_plan(h, F.KERNEL_TBLOCK_IL, 8, 16)
+        assert e.value.status == F.ERR_ARG
+    finally:
+        F.fqnm_destroy(h)
+
+
 @pytest.mark.parametrize("bad", ["cfl", "lut_godunov", "range", "abi", "euler_i32", "n0"])
 def test_create_rejects_invalid_problems(bad):
     n = 100
@@ -279,3 +298,14 @@ def test_w3_reduced_bitexact():
     for plan in PLANS64:
         q, _ = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
         assert np.array_equal(q, ref), plan
+
+
+def test_quantise_entry_point_matches_oracle():
+    rng = np.random.default_rng(17)
+    u = np.concatenate([rng.normal(0, 3, 100003), np.array([2.5, -3.5, 0.5]) * 1e-5])
+    for itype, width in ((F.I32, 32), (F.I64, 64)):
+        got = F.fqnm_quantise(u, 1e-5, itype).astype(np.int64)
+        assert np.array_equal(got, O.quantise(u, 1e-5, width))
+    with pytest.raises(F.FqnmError) as e:
+        F.fqnm_quantise(np.array([1e10]), 1e-5, F.I32)
+    assert e.value.status == F.ERR_RANGE
