@@ -144,6 +144,92 @@ def bench_batch(F, W, stream, reps=3):
                          "speedup_vs_per_instance": t_solo / t_b}}
 
 
+SERVE_COUNT = int(os.environ.get("FQNM_SERVE_COUNT", "200"))
+SERVE_NMAX = int(os.environ.get("FQNM_SERVE_NMAX", str(1 << 15)))
+SERVE_BUDGET = 64 << 20
+
+
+def _serve_inputs(F, W, stream):
+    reqs = W.w5_sod_requests(count=SERVE_COUNT, nmax=SERVE_NMAX)
+    out = []
+    for r in reqs:
+        q0 = F.fqnm_quantise(r.U0.ravel(), r.delta, F.I64, stream)
+        prob = F.make_problem(r.kind, r.delta, r.lam, r.n, bc=F.BC_OUTFLOW, itype=F.I64,
+                              gamma=r.gamma)
+        out.append((prob, q0, r.steps))
+    return out
+
+
+def _serve_run(F, items, arrivals, tick=64):
+    """Submit at the given arrival offsets (None = all at once); returns
+    (wall seconds, latencies, stats)."""
+    srv = F.fqnm_server_create(SERVE_BUDGET, tick)
+    outs = [np.empty_like(q0) for _, q0, _ in items]
+    t0 = F.fqnm_server_now()
+    try:
+        for k, ((prob, q0, steps), out) in enumerate(zip(items, outs)):
+            if arrivals is not None:
+                wait = t0 + arrivals[k] - F.fqnm_server_now()
+                if wait > 0:
+                    time.sleep(wait)
+            F.fqnm_server_submit(srv, prob, q0, steps, out)
+        F.fqnm_server_drain(srv, 900.0)
+        t1 = F.fqnm_server_now()
+        comps = []
+        while True:
+            c = F.fqnm_server_poll(srv, 256)
+            if not c:
+                break
+            comps += c
+        stats = F.fqnm_server_stats_get(srv)
+    finally:
+        F.fqnm_server_destroy(srv)
+    assert all(c["status"] == 0 for c in comps)
+    lat = np.array([c["t_done"] - c["t_submit"] for c in comps])
+    return t1 - t0, lat, stats
+
+
+def bench_serve(F, W, stream):
+    import torch
+    log(f"[bench] W5 {SERVE_COUNT} Sod requests, sizes 2^10..{SERVE_NMAX}")
+    items = _serve_inputs(F, W, stream)
+    work = float(sum(p.n * s for p, _, s in items))
+    mean_work = work / len(items)
+    # closed loop: everything submitted at once -> capacity C
+    t_cl, lat_cl, st_cl = _serve_run(F, items, None)
+    cap = work / t_cl
+    log(f"[bench] W5 closed-loop capacity {cap:.3e} cell-updates/s")
+    res = {"w5_serve": {"requests": len(items), "sizes": f"log-uniform 2^10..{SERVE_NMAX}",
+                        "budget_bytes": SERVE_BUDGET, "cell_updates": work,
+                        "closed_loop_cell_updates_per_s": cap,
+                        "closed_loop_p50_s": float(np.percentile(lat_cl, 50)),
+                        "closed_loop_p99_s": float(np.percentile(lat_cl, 99)),
+                        "peak_bytes": st_cl["peak_bytes"], "ticks": st_cl["ticks"]}}
+    for load in (0.5, 0.7, 0.9):
+        rate = load * cap / mean_work
+        arr = W.poisson_arrivals(len(items), rate, seed=55)
+        t, lat, st = _serve_run(F, items, arr)
+        res["w5_serve"][f"load{load}"] = {
+            "arrival_rate_per_s": rate, "cell_updates_per_s": work / t,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99))}
+        log(f"[bench] W5 load {load}: p50 {np.percentile(lat, 50):.3f}s "
+            f"p99 {np.percentile(lat, 99):.3f}s")
+    # FIFO one request at a time through the single-grid stepper
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for prob, q0, steps in items:
+        h = F.fqnm_create(prob, q0, stream)
+        F.fqnm_step(h, steps)
+        F.fqnm_get_state(h, prob)
+        F.fqnm_destroy(h)
+    t_fifo = time.perf_counter() - t0
+    res["w5_serve"]["fifo_one_at_a_time_cell_updates_per_s"] = work / t_fifo
+    res["w5_serve"]["served_vs_fifo"] = (work / t_cl) / (work / t_fifo)
+    log(f"[bench] W5 FIFO {work / t_fifo:.3e} cell-updates/s")
+    return res
+
+
 def cpu_oracle_rate(w, steps):
     import oracle as O
     op = O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32)
@@ -246,6 +332,9 @@ def main():
     # ---------------- batched: 4096 independent instances --------------------------
     if not args.no_extras and args.only in ("", "batch"):
         extras.update(bench_batch(F, W, stream))
+    # ---------------- served: Sod requests with Poisson arrivals -----------------------
+    if not args.no_extras and args.only in ("", "serve"):
+        extras.update(bench_serve(F, W, stream))
     # ---------------- CPU oracle baseline --------------------------------------------
     if not args.no_cpu:
         csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "600"))

@@ -37,17 +37,7 @@ constexpr int BW = BT / 64;        // wavefronts per workgroup
 constexpr int BMAXV = 128;         // largest cells-per-lane variant
 constexpr int64_t BMAXN = int64_t(BT) * BMAXV;
 
-struct BInst {
-  int64_t off;     // first cell in the concatenated state array
-  int32_t n;
-  int32_t steps;
-  int32_t pol;     // P_UPWIND_POS, P_UPWIND_NEG, P_EO, P_GODUNOV, P_MURMAN_ROE
-  int32_t vec;     // cells per lane
-  int32_t bc;
-  int32_t pad_;
-  double c;        // a*lambda
-  double h;        // (delta*lambda)*0.5
-};
+using BInst = ResidentInst;
 
 template <int POL>
 __device__ __forceinline__ void maps32(const XParams& P, int32_t q, int32_t& pp, int32_t& pm) {
@@ -199,6 +189,33 @@ int64_t resident_max_n(int pol) {
 }
 
 }  // namespace
+
+bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps) {
+  return p.itype == FQNM_I32 && p.n <= resident_max_n(pol) && p.eval != FQNM_EVAL_LUT &&
+         resident_policy(pol) && steps <= INT32_MAX;
+}
+
+int resident_vec(int64_t n) { return pick_vec(n, BT); }
+
+int resident_grid() {
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident, BT, 0) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return std::max(1, cus * per_cu);
+}
+
+hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
+                           int32_t* d_counter, int32_t* d_state, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_zero_counter<<<1, 64, 0, s>>>(d_counter);
+  const int grid = std::min(resident_grid(), static_cast<int>(count));
+  k_batch_resident<<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count, d_counter, d_state);
+  return hipGetLastError();
+}
+
 }  // namespace fqnm
 
 using namespace fqnm;
@@ -219,7 +236,6 @@ struct fqnm_batch {
   int32_t* d_counter = nullptr;
   int32_t n_resident = 0;
   int grid = 0;
-  int lanes = BT;
   std::vector<fqnm_ctx*> big;    // fallback single-grid contexts (borrowing their slices)
   std::vector<int64_t> big_steps;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
@@ -262,12 +278,9 @@ static fqnm_status batch_build_graph(fqnm_batch* b) {
   B_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t e = hipSuccess;
   fqnm_status st = FQNM_OK;
-  if (b->n_resident > 0) {
-    k_zero_counter<<<1, 64, 0, b->stream>>>(b->d_counter);
-    k_batch_resident<<<dim3(b->grid), dim3(BT), 0, b->stream>>>(
-        b->d_insts, b->d_order, b->n_resident, b->d_counter, static_cast<int32_t*>(b->d_state));
-    e = hipGetLastError();
-  }
+  if (b->n_resident > 0)
+    e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->d_counter,
+                        static_cast<int32_t*>(b->d_state), b->stream);
   for (size_t i = 0; i < b->big.size() && e == hipSuccess && st == FQNM_OK; ++i)
     st = fqnm_step(b->big[i], b->big_steps[i]);
   hipGraph_t g = nullptr;
@@ -317,9 +330,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
     b->off.push_back(b->total);
     b->total += (p.n + 1 + per16 - 1) / per16 * per16;  // at least one guard cell behind
     const int pol = policy_of(p, false);
-    const bool res = p.itype == FQNM_I32 && p.n <= resident_max_n(pol) &&
-                     p.eval != FQNM_EVAL_LUT &&
-                     resident_policy(pol) && steps[k] <= INT32_MAX;
+    const bool res = resident_eligible(p, pol, steps[k]);
     b->resident.push_back(res ? 1 : 0);
     if (res) {
       BInst I;
@@ -328,7 +339,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       I.n = static_cast<int32_t>(p.n);
       I.steps = static_cast<int32_t>(steps[k]);
       I.pol = pol;
-      I.vec = pick_vec(p.n, b->lanes);
+      I.vec = resident_vec(p.n);
       I.bc = p.bc;
       XParams x = xparams_of(p);
       I.c = x.c;
@@ -372,13 +383,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
                 hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, b->stream) != hipSuccess))
       st = fail(FQNM_ERR_DEVICE, "copy batch table");
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident, BT, 0) !=
-            hipSuccess || per_cu < 1)
-      per_cu = 1;
-    b->grid = std::max(1, std::min<int>(cus * per_cu, b->n_resident));
+    b->grid = std::min(resident_grid(), b->n_resident);
   }
   // instances outside the resident envelope: single-grid contexts on their slices
   for (int32_t k = 0; k < count && !st; ++k) {

@@ -162,13 +162,13 @@ __device__ __forceinline__ int64_t ghost(int64_t g, int64_t n, int bc) {
   return bc == FQNM_BC_PERIODIC ? wrap_index(g, n) : clamp_index(g, n);
 }
 
-__global__ __launch_bounds__(EB) void k_euler_step(const int64_t* __restrict__ src,
-                                                   int64_t* __restrict__ dst, int64_t n, int bc,
-                                                   EulerParams E, long long* __restrict__ ledger) {
-  __shared__ Prim s_prim[EB];
-  __shared__ int64_t s_T[3][EB];
+// One step of one tile of cells [b0, b0 + ECELLS) of an n-cell problem.
+__device__ __forceinline__ void euler_tile_step(const int64_t* __restrict__ src,
+                                                int64_t* __restrict__ dst, int64_t n, int bc,
+                                                const EulerParams& E, int64_t b0,
+                                                long long* __restrict__ ledger, Prim* s_prim,
+                                                int64_t (*s_T)[EB]) {
   const int t = threadIdx.x;
-  const int64_t b0 = xcd_tile(blockIdx.x, gridDim.x) * ECELLS;
   const int64_t g = b0 - 1 + t;  // cell of this thread
   const int64_t gi = ghost(g, n, bc);
   const int64_t qr = src[gi], qm = src[n + gi], qE = src[2 * n + gi];
@@ -202,12 +202,48 @@ __global__ __launch_bounds__(EB) void k_euler_step(const int64_t* __restrict__ s
   }
 }
 
+__global__ __launch_bounds__(EB) void k_euler_step(const int64_t* __restrict__ src,
+                                                   int64_t* __restrict__ dst, int64_t n, int bc,
+                                                   EulerParams E, long long* __restrict__ ledger) {
+  __shared__ Prim s_prim[EB];
+  __shared__ int64_t s_T[3][EB];
+  const int64_t b0 = xcd_tile(blockIdx.x, gridDim.x) * ECELLS;
+  euler_tile_step(src, dst, n, bc, E, b0, ledger, s_prim, s_T);
+}
+
+// Many independent problems in one launch: block b advances tile tiles[b] of
+// request tiles[b].req by one step, if that request still has a step to take
+// at this position `s` of the current tick.  Each request has its own
+// ping-pong buffers; its source buffer is given by (parity + s) & 1.
+__global__ __launch_bounds__(EB) void k_euler_multi(const EulerTile* __restrict__ tiles,
+                                                    const EulerReq* __restrict__ reqs, int s) {
+  __shared__ Prim s_prim[EB];
+  __shared__ int64_t s_T[3][EB];
+  const EulerTile tl = tiles[blockIdx.x];
+  const EulerReq& R = reqs[tl.req];
+  if (s >= R.steps) return;  // uniform over the block
+  const int par = (R.parity + s) & 1;
+  const int64_t* src = par ? R.buf1 : R.buf0;
+  int64_t* dst = par ? R.buf0 : R.buf1;
+  euler_tile_step(src, dst, R.n, R.bc, R.E, tl.start, R.ledger, s_prim, s_T);
+}
+
 }  // namespace
 
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
                              const EulerParams& E, long long* d_ledger, hipStream_t s) {
   const int64_t blocks = (n + ECELLS - 1) / ECELLS;
   k_euler_step<<<dim3((unsigned)blocks), dim3(EB), 0, s>>>(src, dst, n, bc, E, d_ledger);
+  return hipGetLastError();
+}
+
+int64_t euler_tiles(int64_t n) { return (n + ECELLS - 1) / ECELLS; }
+int64_t euler_tile_cells() { return ECELLS; }
+
+hipError_t launch_euler_multi(const EulerTile* d_tiles, int64_t ntiles, const EulerReq* d_reqs,
+                              int s, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  k_euler_multi<<<dim3((unsigned)ntiles), dim3(EB), 0, st>>>(d_tiles, d_reqs, s);
   return hipGetLastError();
 }
 

@@ -54,6 +54,47 @@ struct EulerParams {
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
                              const EulerParams& E, long long* d_ledger, hipStream_t s);
 
+// Many Euler problems advanced together, one step per launch.
+struct EulerReq {
+  int64_t* buf0;
+  int64_t* buf1;
+  int64_t n;
+  int32_t bc;
+  int32_t steps;   // steps this request takes in the current tick
+  int32_t parity;  // buffer holding its state at the start of the tick
+  int32_t pad_;
+  long long* ledger;
+  EulerParams E;
+};
+struct EulerTile {
+  int32_t req;
+  int32_t pad_;
+  int64_t start;   // first cell of the tile
+};
+int64_t euler_tiles(int64_t n);
+int64_t euler_tile_cells();
+hipError_t launch_euler_multi(const EulerTile* d_tiles, int64_t ntiles, const EulerReq* d_reqs,
+                              int s, hipStream_t st);
+
+// Register-resident scalar instances (int32 cells), run by the persistent
+// batch kernel: each instance advances `steps` steps in place.
+struct ResidentInst {
+  int64_t off;     // first cell in the state array
+  int32_t n;
+  int32_t steps;
+  int32_t pol;
+  int32_t vec;
+  int32_t bc;
+  int32_t pad_;
+  double c;
+  double h;
+};
+bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps);
+int resident_vec(int64_t n);
+int resident_grid();
+hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
+                           int32_t* d_counter, int32_t* d_state, hipStream_t s);
+
 // Thread-local error message of the public ABI.
 void set_error(const std::string& msg);
 

@@ -1,0 +1,131 @@
+"""GPU tests of the continuous-batching server: every request's final state
+equals the oracle's (so it is the same alone and in any mix), admission
+respects the device budget, requests arriving while others run are admitted
+as memory frees up, and oversize requests are refused."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_06947_amd import fqnm as F
+from paper_2604_06947_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    F.lib()
+
+
+def sod(n, seed, kind=F.FLUX_EULER_ROE_EF):
+    rng = np.random.default_rng(seed)
+    left = (rng.uniform(0.8, 1.2), 0.0, rng.uniform(0.8, 1.2))
+    right = (0.125 * rng.uniform(0.8, 1.2), 0.0, 0.1 * rng.uniform(0.8, 1.2))
+    r = W.sod_request(n, left, right, kind=kind)
+    prob = F.make_problem(kind, r.delta, r.lam, n, bc=F.BC_OUTFLOW, itype=F.I64, gamma=1.4)
+    q0 = np.stack([O.quantise(r.U0[c], r.delta, 64) for c in range(3)])
+    op = O.Problem(kind, r.delta, r.lam, bc=O.OUTFLOW, width=64, gamma=1.4)
+    return prob, q0, r.steps, op
+
+
+def scalar(n, seed, flux, itype=F.I32, lut=False, bc=F.BC_PERIODIC):
+    u0 = W.random_smooth_step(n, seed=seed, b=0.3)
+    delta = 1e-4 if itype == F.I32 else 1e-7
+    lam = 0.45 / float(np.max(np.abs(u0))) if flux != F.FLUX_UPWIND else 0.6
+    prob = F.make_problem(flux, delta, lam, n, bc=bc, itype=itype,
+                          eval_=F.EVAL_LUT if lut else F.EVAL_DIRECT)
+    width = 32 if itype == F.I32 else 64
+    q0 = O.quantise(u0, delta, width)
+    op = O.Problem(O.UPWIND if flux == F.FLUX_UPWIND else O.BURGERS_EO, delta, lam, bc=bc,
+                   width=width)
+    return prob, q0, 300 + seed % 200, op
+
+
+def oracle_final(prob, q0, steps, op):
+    if q0.ndim == 2:
+        return O.step_euler(op, q0, steps)
+    return O.step(op, q0, steps)
+
+
+def mixed_requests():
+    reqs = [sod(n, seed=i) for i, n in enumerate([64, 300, 1024, 1500, 2000, 600])]
+    reqs += [scalar(n, 10 + i, F.FLUX_BURGERS_EO) for i, n in enumerate([5, 700, 4096, 30000])]
+    reqs += [scalar(5000, 20, F.FLUX_UPWIND), scalar(3000, 21, F.FLUX_BURGERS_EO, lut=True),
+             scalar(2500, 22, F.FLUX_BURGERS_EO, itype=F.I64, bc=F.BC_OUTFLOW),
+             scalar(80000, 23, F.FLUX_UPWIND)]
+    return reqs
+
+
+def run_server(reqs, budget, tick, stagger=0.0):
+    srv = F.fqnm_server_create(budget, tick)
+    outs = [np.empty_like(q0.ravel().astype(np.int32 if p.itype == F.I32 else np.int64))
+            for p, q0, _, _ in reqs]
+    ids = []
+    try:
+        def submit_all():
+            for (p, q0, steps, _), out in zip(reqs, outs):
+                dt = np.int32 if p.itype == F.I32 else np.int64
+                ids.append(F.fqnm_server_submit(srv, p, q0.astype(dt), steps, out))
+                if stagger:
+                    time.sleep(stagger)
+        th = threading.Thread(target=submit_all)
+        th.start()
+        th.join()
+        F.fqnm_server_drain(srv, 300.0)
+        comps = []
+        while True:
+            c = F.fqnm_server_poll(srv, 64)
+            if not c:
+                break
+            comps += c
+        stats = F.fqnm_server_stats_get(srv)
+    finally:
+        F.fqnm_server_destroy(srv)
+    return outs, ids, comps, stats
+
+
+def test_mixed_requests_match_oracle_alone_and_in_mix():
+    reqs = mixed_requests()
+    outs, ids, comps, stats = run_server(reqs, 256 << 20, 64, stagger=0.002)
+    assert len(comps) == len(reqs) and all(c["status"] == 0 for c in comps)
+    by_id = {c["id"]: c for c in comps}
+    for (p, q0, steps, op), out, rid in zip(reqs, outs, ids):
+        ref = oracle_final(p, q0, steps, op)
+        assert np.array_equal(out.astype(np.int64).reshape(ref.shape), ref), (p.flux, p.n)
+        c = by_id[rid]
+        assert c["t_submit"] <= c["t_admit"] <= c["t_done"] and c["steps"] == steps
+    # the same request alone gives the same integers
+    p, q0, steps, op = reqs[3]
+    outs1, _, _, _ = run_server([reqs[3]], 64 << 20, 17)
+    assert np.array_equal(outs1[0], outs[3])
+    assert stats["completed"] == len(reqs)
+
+
+def test_small_budget_queues_and_completes():
+    reqs = [sod(n, seed=30 + i) for i, n in enumerate([1000, 1200, 900, 1100, 1300, 800])]
+    # each request needs ~2*3*n*8 bytes; the budget holds about two at a time
+    budget = 2 * (2 * 3 * 1300 * 8 + 4096)
+    outs, ids, comps, stats = run_server(reqs, budget, 32)
+    assert stats["peak_bytes"] <= budget and stats["completed"] == len(reqs)
+    admits = sorted(c["t_admit"] for c in comps)
+    dones = sorted(c["t_done"] for c in comps)
+    assert admits[-1] > dones[0]  # later requests waited for memory to free up
+    for (p, q0, steps, op), out in zip(reqs, outs):
+        assert np.array_equal(out.reshape(3, -1), oracle_final(p, q0, steps, op))
+
+
+def test_oversize_request_refused():
+    srv = F.fqnm_server_create(1 << 20, 8)
+    try:
+        p, q0, steps, _ = sod(100000, seed=1)
+        out = np.empty(q0.size, np.int64)
+        with pytest.raises(F.FqnmError) as e:
+            F.fqnm_server_submit(srv, p, q0, steps, out)
+        assert e.value.status == F.ERR_OOM
+    finally:
+        F.fqnm_server_destroy(srv)
