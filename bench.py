@@ -31,6 +31,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_sources_sha():
+    import hashlib
+    from paper_2604_06947_amd import plans
+    pkg = os.path.join(ROOT, "paper_2604_06947_amd")
+    h = hashlib.sha256()
+    for rel in plans.KERNEL_SOURCES:
+        with open(os.path.join(pkg, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -253,6 +264,24 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n, "copies": 3}))
 
 
+def run_extras_only(args, F, W, plans, stream):
+    """Profiling aid: run one extra workload without the headline line."""
+    extras = {}
+    if args.only == "w3":
+        w3 = W.w3_nyquist_advection(r=1e-3)
+        p3 = F.make_problem(F.FLUX_UPWIND, w3.delta, w3.lam, w3.n, itype=F.I64, a=1.0)
+        for tag, pl in (("stream", plans.STREAM_PLAN_W3), ("tblock", plans.BENCH_PLAN_W3)):
+            S3 = Solver(F, p3, w3.u0, pl, stream)
+            sec3, _ = time_solver(S3, w3.steps, max(args.steps, 1), args.warmup)
+            S3.close()
+            extras[f"w3_r0.001_{tag}"] = {"cell_updates_per_s": w3.n * w3.steps / sec3}
+    elif args.only == "batch":
+        extras.update(bench_batch(F, W, stream))
+    elif args.only == "serve":
+        extras.update(bench_serve(F, W, stream))
+    print(json.dumps({"extras": extras}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -276,6 +305,8 @@ def main():
 
     # ---------------- headline: Burgers EO LUT, 2^20 int32, 10000 steps -------------
     w = W.w2_burgers_step()
+    if args.only not in ("", "w2"):
+        return run_extras_only(args, F, W, plans, stream)
     prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
                           eval_=F.EVAL_LUT)
     log(f"[bench] W2 {w.name}")
@@ -302,8 +333,16 @@ def main():
                    "plan": {"kernel": "tblock" if plan["kernel"] else "stream",
                             "vec": plan["vec"], "depth": plan["depth"]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_tblock<int, P_LUT, 16>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (plans.TRAFFIC_BYTES_PER_LAUNCH["w2"]
+                                 if kernel_sources_sha() == plans.MEASURED_SOURCES_SHA
+                                 and tuple(plan.values())[:3] == (plans.BENCH_PLAN_W2[0],
+                                                                   plans.BENCH_PLAN_W2[1],
+                                                                   plans.BENCH_PLAN_W2[2])
+                                 else None),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": 8 * units,
+                     "kernel": f"k_tblock<int, P_LUT, {plan['vec']}>",
                      "bytes_per_cell_update": 8, "cell_updates_per_launch": units,
                      "avg_launch_us": launch_s * 1e6},
         "hbm_roofline_cell_updates_per_s": HBM_PEAK_GBS * 1e9 / 8.0,

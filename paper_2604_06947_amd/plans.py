@@ -4,8 +4,18 @@ tests run the same plans at full size."""
 from .fqnm import KERNEL_STREAM, KERNEL_TBLOCK
 
 # Burgers, 2^20 int32 cells, Engquist-Osher LUT, 10000 steps
-BENCH_PLAN_W2 = (KERNEL_TBLOCK, 16, 32)
+BENCH_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
 # near-Nyquist advection, 2^24 int64 cells, 2000 steps
-BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 16)
+BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
 # the one-step-per-pass streaming plan reported beside it
-STREAM_PLAN_W3 = (KERNEL_STREAM, 4, 1)
+STREAM_PLAN_W3 = (KERNEL_STREAM, 2, 1)
+
+# HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a plain device copy of known size (see profiles/).
+# Valid only for the kernel sources they were measured on: the benchmark
+# reports null when the hash of those sources differs.
+KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
+MEASURED_SOURCES_SHA = "3bc4a929a5b53294"
+TRAFFIC_BYTES_PER_LAUNCH = {
+    "w2": 11459 * 1024,  # k_tblock<int, P_LUT, 4>, 24 steps per launch
+}
