@@ -203,8 +203,8 @@ void store_plan(const std::string& key, const fqnm_plan& pl) {
 fqnm_plan default_plan(const fqnm_problem& p) {
   fqnm_plan pl;
   pl.kernel = K_TBLOCK;
-  pl.vec = p.itype == FQNM_I32 ? 4 : 8;
-  pl.depth = 24;
+  pl.vec = p.itype == FQNM_I32 && p.eval != FQNM_EVAL_LUT ? 4 : 8;
+  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 64 : 24;
   pl.eval = 0;
   return pl;
 }

@@ -140,14 +140,44 @@ __device__ __forceinline__ IT wsub(IT a, IT b) {
   return static_cast<IT>(static_cast<U>(a) - static_cast<U>(b));
 }
 
-// Cross-lane moves within a 64-wide wavefront.
+// Cross-lane moves within a 64-wide wavefront, as DPP wavefront shifts (a
+// modifier on a VALU move, no LDS round trip).  gfx9 controls: 0x130 shift
+// left (lane l takes lane l+1), 0x138 shift right (lane l takes lane l-1),
+// 0x134 / 0x13C the rotating forms.  The end lane of a shift keeps its own
+// value.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL, typename IT>
+__device__ __forceinline__ IT dpp_move(IT v) {
+  if constexpr (sizeof(IT) == 4) {
+    return static_cast<IT>(dpp32<CTRL>(static_cast<int>(v)));
+  } else {
+    const uint64_t u = static_cast<uint64_t>(v);
+    const int lo = dpp32<CTRL>(static_cast<int>(static_cast<uint32_t>(u)));
+    const int hi = dpp32<CTRL>(static_cast<int>(static_cast<uint32_t>(u >> 32)));
+    return static_cast<IT>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                           static_cast<uint32_t>(lo));
+  }
+}
+
 template <typename IT>
 __device__ __forceinline__ IT lane_from_next(IT v) {  // lane l receives lane l+1 (lane 63: own)
-  return __shfl_down(v, 1, 64);
+  return dpp_move<0x130, IT>(v);
 }
 template <typename IT>
 __device__ __forceinline__ IT lane_from_prev(IT v) {  // lane l receives lane l-1 (lane 0: own)
-  return __shfl_up(v, 1, 64);
+  return dpp_move<0x138, IT>(v);
+}
+template <typename IT>
+__device__ __forceinline__ IT rotate_from_next(IT v) {  // lane l receives lane (l+1) mod 64
+  return dpp_move<0x134, IT>(v);
+}
+template <typename IT>
+__device__ __forceinline__ IT rotate_from_prev(IT v) {  // lane l receives lane (l-1) mod 64
+  return dpp_move<0x13C, IT>(v);
 }
 
 // Map block index to a tile index so that consecutive tiles land on the same

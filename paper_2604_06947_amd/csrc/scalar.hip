@@ -109,6 +109,31 @@ __device__ __forceinline__ void cell_maps(const XParams& P, const LutView& L, IT
   }
 }
 
+// A wavefront-private slice of the int32 table in LDS: entries for states
+// [lo, lo + last].  Indices are clamped into the slice, so a discarded halo
+// lane holding any value reads inside it.
+constexpr int TB_WIN = 512;
+
+struct LdsWindow {
+  const int2* e;
+  int32_t lo;
+  int32_t last;
+};
+
+template <typename IT, int POL, bool WIN>
+__device__ __forceinline__ void cell_maps_w(const XParams& P, const LutView& L,
+                                            const LdsWindow& Wn, IT q, IT& pp, IT& pm) {
+  if constexpr (WIN) {
+    int32_t i = static_cast<int32_t>(q) - Wn.lo;
+    i = i < 0 ? 0 : (i > Wn.last ? Wn.last : i);
+    const int2 e = Wn.e[i];
+    pp = static_cast<IT>(e.x);
+    pm = static_cast<IT>(e.y);
+  } else {
+    cell_maps<IT, POL>(P, L, q, pp, pm);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K1: one step per pass.
 // ---------------------------------------------------------------------------
@@ -187,14 +212,15 @@ __global__ __launch_bounds__(256) void k_stream(const IT* __restrict__ src, IT* 
 // interface of a lane needs the next lane's first cell, the first cell's left
 // interface arrives from the previous lane.  With `edge` the outflow rules of
 // the domain ends apply at global positions g0+j (frozen outside [0, n)).
-template <typename IT, int POL, int V, bool EDGE>
-__device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, IT (&q)[V],
-                                        int64_t g0, int64_t n, bool own_right, long long& led) {
+template <typename IT, int POL, int V, bool EDGE, bool WIN = false>
+__device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, const LdsWindow& Wn,
+                                        IT (&q)[V], int64_t g0, int64_t n, bool own_right,
+                                        long long& led) {
   IT F[V];
   if constexpr (IsSplit<POL>::value) {
     IT pp[V], pm[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) cell_maps<IT, POL>(P, L, q[j], pp[j], pm[j]);
+    for (int j = 0; j < V; ++j) cell_maps_w<IT, POL, WIN>(P, L, Wn, q[j], pp[j], pm[j]);
     const IT pmn = lane_from_next<IT>(pm[0]);
     if constexpr (!EDGE) {
 #pragma unroll
@@ -268,11 +294,58 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
   }
   long long led = 0;
   const LutView L = lut_view(P);
-  if (inside || bc == FQNM_BC_PERIODIC) {
-    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, q, g0, n, false, led);
-  } else {
-    const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
-    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, q, g0, n, own_right, led);
+  const bool plain = inside || bc == FQNM_BC_PERIODIC;
+  const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
+  bool done = false;
+  if constexpr (POL == P_LUT && sizeof(IT) == 4) {
+    // Every in-domain state of this tile stays inside the tile's initial
+    // range for the whole launch (each update is a monotone function of its
+    // three-cell stencil), so that slice of the table is all it reads.
+    __shared__ int2 s_win[4][TB_WIN];
+    int32_t mn = static_cast<int32_t>(q[0]), mx = mn;
+#pragma unroll
+    for (int j = 1; j < V; ++j) {
+      mn = q[j] < mn ? static_cast<int32_t>(q[j]) : mn;
+      mx = q[j] > mx ? static_cast<int32_t>(q[j]) : mx;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int32_t a = __shfl_xor(mn, off, 64), b = __shfl_xor(mx, off, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    const int64_t span = static_cast<int64_t>(mx) - mn;
+    if (span < TB_WIN) {  // wavefront-uniform
+      int2* w = s_win[wave];
+      for (int i = lane; i <= span; i += 64) {
+        const uint32_t off =
+            (static_cast<uint32_t>(mn) + static_cast<uint32_t>(i) - static_cast<uint32_t>(P.lut_lo))
+            << 3;
+        const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
+        w[i] = make_int2(e[0], e[1]);
+      }
+      // the slice written by some lanes is read by all lanes of this wavefront
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const LdsWindow Wn{w, mn, static_cast<int32_t>(span)};
+      if (plain) {
+        for (int s = 0; s < ksteps; ++s)
+          tb_step<IT, POL, V, false, true>(P, L, Wn, q, g0, n, false, led);
+      } else {
+        for (int s = 0; s < ksteps; ++s)
+          tb_step<IT, POL, V, true, true>(P, L, Wn, q, g0, n, own_right, led);
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+    const LdsWindow Wn{nullptr, 0, 0};
+    if (plain) {
+      for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
+    } else {
+      for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, Wn, q, g0, n, own_right, led);
+    }
   }
   const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;
   if (lane >= lane_lo && lane < lane_hi) {
@@ -293,25 +366,10 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
 // Position p = j*64 + lane of the wavefront tile holds slot j of that lane, so
 // a table read of slot j touches the maps of 64 consecutive cells (a few cache
 // lines) instead of 64 cells spread V apart.  Every neighbour is one lane
-// away: values move by a rotation of the wavefront (ds_bpermute), and the
-// lane at the end of a slot takes the value rotated out of the adjacent slot.
+// away: values move by a rotation of the wavefront (DPP), and the lane at the
+// end of a slot takes the value rotated out of the adjacent slot.
 // The halo is a whole number of slots (khalo % 64 == 0).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
-
-template <typename IT>
-__device__ __forceinline__ IT rotate(int addr, IT v) {
-  if constexpr (sizeof(IT) == 4) {
-    return static_cast<IT>(bperm(addr, static_cast<int>(v)));
-  } else {
-    const uint64_t u = static_cast<uint64_t>(v);
-    const int lo = bperm(addr, static_cast<int>(static_cast<uint32_t>(u)));
-    const int hi = bperm(addr, static_cast<int>(static_cast<uint32_t>(u >> 32)));
-    return static_cast<IT>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
-                           static_cast<uint32_t>(lo));
-  }
-}
-
 template <typename IT, int POL, int V, bool EDGE>
 __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (&q)[V], int lane,
                                         int a_next,
@@ -323,7 +381,7 @@ __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (
   // pm of the right neighbour: lane l+1 of the same slot, or lane 0 of slot j+1
   IT rm[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) rm[j] = rotate<IT>(a_next, pm[j]);
+  for (int j = 0; j < V; ++j) rm[j] = rotate_from_next<IT>(pm[j]);
   if constexpr (!EDGE) {
 #pragma unroll
     for (int j = 0; j < V; ++j) {
@@ -333,7 +391,7 @@ __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (
   } else {
     IT rp[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) rp[j] = rotate<IT>(a_next, pp[j]);
+    for (int j = 0; j < V; ++j) rp[j] = rotate_from_next<IT>(pp[j]);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const int64_t g = wstart + j * 64 + lane;
@@ -350,7 +408,7 @@ __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (
   // F of the left interface: lane l-1 of the same slot, or lane 63 of slot j-1
   IT rf[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) rf[j] = rotate<IT>(a_prev, F[j]);
+  for (int j = 0; j < V; ++j) rf[j] = rotate_from_prev<IT>(F[j]);
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     const IT Fl = (lane == 0 && j > 0) ? rf[j - 1] : rf[j];

@@ -4,7 +4,7 @@ tests run the same plans at full size."""
 from .fqnm import KERNEL_STREAM, KERNEL_TBLOCK
 
 # Burgers, 2^20 int32 cells, Engquist-Osher LUT, 10000 steps
-BENCH_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
+BENCH_PLAN_W2 = (KERNEL_TBLOCK, 8, 64)
 # near-Nyquist advection, 2^24 int64 cells, 2000 steps
 BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
 # the one-step-per-pass streaming plan reported beside it

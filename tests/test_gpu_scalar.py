@@ -21,7 +21,7 @@ KIND_F2O = {F.FLUX_UPWIND: O.UPWIND, F.FLUX_BURGERS_EO: O.BURGERS_EO,
 
 PLANS32 = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_STREAM, 16, 1),
            (F.KERNEL_TBLOCK, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 8, 8),
-           (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96),
+           (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96), (F.KERNEL_TBLOCK, 8, 64),
            (F.KERNEL_TBLOCK_IL, 4, 16), (F.KERNEL_TBLOCK_IL, 8, 64), (F.KERNEL_TBLOCK_IL, 16, 100)]
 PLANS64 = [(F.KERNEL_STREAM, 2, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_TBLOCK, 2, 2),
            (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48),
