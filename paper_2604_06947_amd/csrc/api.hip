@@ -203,8 +203,8 @@ void store_plan(const std::string& key, const fqnm_plan& pl) {
 fqnm_plan default_plan(const fqnm_problem& p) {
   fqnm_plan pl;
   pl.kernel = K_TBLOCK;
-  pl.vec = p.itype == FQNM_I32 && p.eval != FQNM_EVAL_LUT ? 4 : 8;
-  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 64 : 24;
+  pl.vec = p.itype == FQNM_I32 ? 4 : 8;
+  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 48 : 24;
   pl.eval = 0;
   return pl;
 }
@@ -589,8 +589,7 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (!ctx || !plan) return fail(FQNM_ERR_ARG, "NULL argument");
   if (ctx->euler) return fail(FQNM_ERR_UNSUPPORTED, "Euler contexts have a fixed plan");
   fqnm_plan pl = ctx->plan;
-  if (plan->kernel == K_STREAM || plan->kernel == K_TBLOCK || plan->kernel == K_TBLOCK_IL)
-    pl.kernel = plan->kernel;
+  if (plan->kernel >= K_STREAM && plan->kernel <= K_TBLOCK_B8) pl.kernel = plan->kernel;
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
   if (plan->depth) pl.depth = plan->depth;
@@ -599,7 +598,8 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (pl.kernel != K_STREAM) {
     if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth must be >= 1");
     const int kh = scalar_halo(pl.kernel, pl.vec, pl.depth);
-    if (64 * pl.vec - 2 * kh < pl.vec) return fail(FQNM_ERR_ARG, "depth too large for vec");
+    if (scalar_tile_positions(pl.kernel, pl.vec) - 2 * kh < pl.vec)
+      return fail(FQNM_ERR_ARG, "depth too large for vec");
   }
   ctx->plan = pl;
   return FQNM_OK;
@@ -631,6 +631,13 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     for (int d : {4, 8, 16, 32, 64, 96}) {
       const int kh = scalar_halo(K_TBLOCK, v, d);
       if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
+    }
+    for (int kb : {K_TBLOCK_B2, K_TBLOCK_B4, K_TBLOCK_B8}) {
+      for (int d : {24, 48, 64, 96}) {
+        const int kh = scalar_halo(kb, v, d);
+        if (scalar_tile_positions(kb, v) - 2 * kh >= scalar_tile_positions(kb, v) / 2)
+          cand.push_back({kb, v, d, 0});
+      }
     }
     if (scalar_variant_available(ctx->prob.itype, ctx->pol, K_TBLOCK_IL, v)) {
       for (int d : {16, 32, 64, 128}) {

@@ -12,7 +12,14 @@
 
 namespace fqnm {
 
-enum : int { K_STREAM = 0, K_TBLOCK = 1, K_TBLOCK_IL = 2 };
+enum : int {
+  K_STREAM = 0,
+  K_TBLOCK = 1,
+  K_TBLOCK_IL = 2,
+  K_TBLOCK_B2 = 3,  // workgroup tiles of 2, 4 or 8 wavefronts
+  K_TBLOCK_B4 = 4,
+  K_TBLOCK_B8 = 5
+};
 
 // Per-block partial results of the reduction kernel (one record per block).
 struct ReducePartial {
@@ -32,6 +39,7 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
                          long long* d_ledger, hipStream_t s);
 bool scalar_variant_available(int itype, int pol, int kernel, int vec);
 int scalar_halo(int kernel, int vec, int ksteps);  // halo width of the temporal-blocking kernels
+int scalar_tile_positions(int kernel, int vec);     // cells loaded per tile
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
                             int64_t count, hipStream_t s);

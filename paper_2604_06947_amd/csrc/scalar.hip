@@ -75,6 +75,7 @@ __device__ __forceinline__ int64_t ghost_index(int64_t g, int64_t n, int bc) {
 // discarded halo lanes can ever be out of range.
 struct LutView {
   __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t bias;  // -8*lo modulo 2^32
 };
 
 __device__ __forceinline__ LutView lut_view(const XParams& P) {
@@ -82,6 +83,7 @@ __device__ __forceinline__ LutView lut_view(const XParams& P) {
   const int64_t bytes = (P.lut_last + 1) * 8;
   v.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(P.lut), static_cast<short>(0),
                                              static_cast<int>(bytes), 0x00020000);
+  v.bias = 0u - (static_cast<uint32_t>(P.lut_lo) << 3);
   return v;
 }
 
@@ -90,7 +92,8 @@ __device__ __forceinline__ void cell_maps(const XParams& P, const LutView& L, IT
                                           IT& pm) {
   if constexpr (POL == P_LUT) {
     if constexpr (sizeof(IT) == 4) {
-      const uint32_t off = (static_cast<uint32_t>(q) - static_cast<uint32_t>(P.lut_lo)) << 3;
+      // byte offset 8*(q - lo), in 32-bit wrapping arithmetic: one shift-add
+      const uint32_t off = (static_cast<uint32_t>(q) << 3) + L.bias;
       const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
       pp = static_cast<IT>(e[0]);
       pm = static_cast<IT>(e[1]);
@@ -114,21 +117,27 @@ __device__ __forceinline__ void cell_maps(const XParams& P, const LutView& L, IT
 // lane holding any value reads inside it.
 constexpr int TB_WIN = 512;
 
+typedef __attribute__((address_space(3))) int2 lds_int2;
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+
 struct LdsWindow {
-  const int2* e;
-  int32_t lo;
-  int32_t last;
+  uint32_t bias;  // LDS byte address of the slice minus 8*lo, modulo 2^32
+  uint32_t end;   // LDS byte address of the slice's last entry
 };
 
 template <typename IT, int POL, bool WIN>
 __device__ __forceinline__ void cell_maps_w(const XParams& P, const LutView& L,
                                             const LdsWindow& Wn, IT q, IT& pp, IT& pm) {
   if constexpr (WIN) {
-    int32_t i = static_cast<int32_t>(q) - Wn.lo;
-    i = i < 0 ? 0 : (i > Wn.last ? Wn.last : i);
-    const int2 e = Wn.e[i];
-    pp = static_cast<IT>(e.x);
-    pm = static_cast<IT>(e.y);
+    // LDS byte address of entry q: one shift-add, then one unsigned min.  A
+    // state past the slice clamps to its last entry; one below it lands lower
+    // in this workgroup's LDS (or wraps high and clamps): always inside the
+    // allocation, and only discarded halo lanes can hold such states.
+    uint32_t a = (static_cast<uint32_t>(q) << 3) + Wn.bias;
+    a = a < Wn.end ? a : Wn.end;
+    const uint64_t e = *(lds_u64*)(static_cast<uintptr_t>(a));
+    pp = static_cast<IT>(static_cast<int32_t>(static_cast<uint32_t>(e)));
+    pm = static_cast<IT>(static_cast<int32_t>(static_cast<uint32_t>(e >> 32)));
   } else {
     cell_maps<IT, POL>(P, L, q, pp, pm);
   }
@@ -328,7 +337,10 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const LdsWindow Wn{w, mn, static_cast<int32_t>(span)};
+      const uint32_t base =
+          static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(w)));
+      const LdsWindow Wn{base - (static_cast<uint32_t>(mn) << 3),
+                         base + (static_cast<uint32_t>(span) << 3)};
       if (plain) {
         for (int s = 0; s < ksteps; ++s)
           tb_step<IT, POL, V, false, true>(P, L, Wn, q, g0, n, false, led);
@@ -340,7 +352,7 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
     }
   }
   if (!done) {
-    const LdsWindow Wn{nullptr, 0, 0};
+    const LdsWindow Wn{0u, 0u};
     if (plain) {
       for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
     } else {
@@ -349,6 +361,224 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
   }
   const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;
   if (lane >= lane_lo && lane < lane_hi) {
+    if (g0 + V <= n) {
+      store_vec<IT, V>(dst + g0, q);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (g0 + j < n) dst[g0 + j] = q[j];
+    }
+  }
+  if (led != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
+}
+
+// ---------------------------------------------------------------------------
+// K4: temporal blocking with a workgroup tile.  The NW wavefronts of a
+// workgroup hold one contiguous tile of NW*64*V cells (V per lane, lanes in
+// order), so the halo is paid once per workgroup instead of once per
+// wavefront.  Each step every wavefront publishes its first and last cell in
+// LDS (double buffered by step parity, one barrier per step); the edge lanes
+// evaluate the one extra map or transfer they need from those cells.  For
+// int32 tables the workgroup stages the slice of the table its tile can reach
+// in LDS, as K2 does per wavefront.
+// ---------------------------------------------------------------------------
+constexpr int TBB_WIN = 2048;
+
+template <typename IT, int POL, bool WIN>
+__device__ __forceinline__ IT map_plus(const XParams& P, const LutView& L, const LdsWindow& Wn,
+                                       IT q) {
+  IT a, b;
+  cell_maps_w<IT, POL, WIN>(P, L, Wn, q, a, b);
+  return a;
+}
+template <typename IT, int POL, bool WIN>
+__device__ __forceinline__ IT map_minus(const XParams& P, const LutView& L, const LdsWindow& Wn,
+                                        IT q) {
+  IT a, b;
+  cell_maps_w<IT, POL, WIN>(P, L, Wn, q, a, b);
+  return b;
+}
+
+// Edge cells of every wavefront, in LDS: [parity][first, last][wave].
+template <typename IT>
+using lds_ptr = __attribute__((address_space(3))) IT*;
+
+template <typename IT, int POL, int V, int NW, bool EDGE, bool WIN>
+__device__ __forceinline__ void blk_step(const XParams& P, const LutView& L, const LdsWindow& Wn,
+                                         IT (&q)[V], lds_ptr<IT> s_edge, int s, int wave,
+                                         int lane, int64_t g0, int64_t n, bool own_right,
+                                         long long& led) {
+  const int b = s & 1;
+  if (lane == 0) s_edge[(b * 2 + 0) * NW + wave] = q[0];
+  if (lane == 63) s_edge[(b * 2 + 1) * NW + wave] = q[V - 1];
+  __syncthreads();
+  // neighbours across wavefronts (the tile's two ends are halo and may hold anything)
+  const IT q_next = (wave + 1 < NW) ? s_edge[(b * 2 + 0) * NW + wave + 1] : q[V - 1];
+  const IT q_prev = (wave > 0) ? s_edge[(b * 2 + 1) * NW + wave - 1] : q[0];
+  IT F[V];
+  IT Fl;
+  if constexpr (IsSplit<POL>::value) {
+    IT pp[V], pm[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) cell_maps_w<IT, POL, WIN>(P, L, Wn, q[j], pp[j], pm[j]);
+    IT pmn = lane_from_next<IT>(pm[0]);
+    IT ppn = EDGE ? lane_from_next<IT>(pp[0]) : IT(0);
+    if (lane == 63) {
+      IT a, c;
+      cell_maps_w<IT, POL, WIN>(P, L, Wn, q_next, a, c);
+      pmn = c;
+      ppn = a;
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const IT pmR = j + 1 < V ? pm[j + 1] : pmn;
+      IT f = pp[j] + pmR;
+      if constexpr (EDGE) {
+        const int64_t g = g0 + j;
+        const IT ppR = j + 1 < V ? pp[j + 1] : ppn;
+        if (g == -1) f = ppR + pmR;         // F_{-1/2} = T(q_0, q_0)
+        if (g == n - 1) f = pp[j] + pm[j];  // F_{n-1/2} = T(q_{n-1}, q_{n-1})
+        if (g == -1) led += static_cast<long long>(f);
+        if (g == n - 1 && own_right) led -= static_cast<long long>(f);
+      }
+      F[j] = f;
+    }
+    Fl = lane_from_prev<IT>(F[V - 1]);
+    if (lane == 0) Fl = map_plus<IT, POL, WIN>(P, L, Wn, q_prev) + pm[0];
+    if constexpr (EDGE) {
+      // the interface in front of this lane's first cell, if it is F_{-1/2}
+      if (lane == 0 && g0 - 1 == -1) Fl = pp[0] + pm[0];
+    }
+  } else {
+    IT qn = lane_from_next<IT>(q[0]);
+    if (lane == 63) qn = q_next;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      IT qL = q[j];
+      IT qR = j + 1 < V ? q[j + 1] : qn;
+      if constexpr (EDGE) {
+        const int64_t g = g0 + j;
+        if (g == -1) qL = qR;
+        if (g == n - 1) qR = qL;
+        F[j] = transfer<IT, POL>(P, qL, qR);
+        if (g == -1) led += static_cast<long long>(F[j]);
+        if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
+      } else {
+        F[j] = transfer<IT, POL>(P, qL, qR);
+      }
+    }
+    Fl = lane_from_prev<IT>(F[V - 1]);
+    if (lane == 0) Fl = transfer<IT, POL>(P, q_prev, q[0]);
+    if constexpr (EDGE) {
+      if (lane == 0 && g0 - 1 == -1) Fl = transfer<IT, POL>(P, q[0], q[0]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const IT d = wsub<IT>(F[j], j == 0 ? Fl : F[j - 1]);
+    if constexpr (EDGE) {
+      const int64_t g = g0 + j;
+      if (g >= 0 && g < n) q[j] = wsub<IT>(q[j], d);
+    } else {
+      q[j] = wsub<IT>(q[j], d);
+    }
+  }
+}
+
+template <typename IT, int POL, int V, int NW>
+__global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ src,
+                                                        IT* __restrict__ dst, int64_t n, int bc,
+                                                        int ksteps, int khalo, int64_t ntiles,
+                                                        XParams P,
+                                                        long long* __restrict__ ledger) {
+  __shared__ IT s_edge_mem[2 * 2 * NW];
+  const lds_ptr<IT> s_edge = (lds_ptr<IT>)(s_edge_mem);
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;  // uniform over the workgroup
+  constexpr int PW = NW * 64 * V;
+  const int64_t T = PW - 2 * khalo;
+  const int64_t tstart = tile * T;
+  const int64_t wstart = tstart - khalo;
+  const int64_t g0 = wstart + static_cast<int64_t>(threadIdx.x) * V;
+  const bool inside = wstart >= 0 && wstart + PW <= n;  // workgroup-uniform
+  IT q[V];
+  if (inside) {
+    load_vec<IT, V>(src + g0, q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = src[ghost_index(g0 + j, n, bc)];
+  }
+  long long led = 0;
+  const LutView L = lut_view(P);
+  const bool plain = inside || bc == FQNM_BC_PERIODIC;
+  const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
+  bool done = false;
+  if constexpr (POL == P_LUT && sizeof(IT) == 4) {
+    __shared__ int2 s_win[TBB_WIN];
+    __shared__ int32_t s_mm[2][NW];
+    int32_t mn = static_cast<int32_t>(q[0]), mx = mn;
+#pragma unroll
+    for (int j = 1; j < V; ++j) {
+      mn = q[j] < mn ? static_cast<int32_t>(q[j]) : mn;
+      mx = q[j] > mx ? static_cast<int32_t>(q[j]) : mx;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int32_t a = __shfl_xor(mn, off, 64), c = __shfl_xor(mx, off, 64);
+      mn = a < mn ? a : mn;
+      mx = c > mx ? c : mx;
+    }
+    if (lane == 0) {
+      s_mm[0][wave] = mn;
+      s_mm[1][wave] = mx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      mn = s_mm[0][w] < mn ? s_mm[0][w] : mn;
+      mx = s_mm[1][w] > mx ? s_mm[1][w] : mx;
+    }
+    const int64_t span = static_cast<int64_t>(mx) - mn;
+    if (span < TBB_WIN) {  // workgroup-uniform
+      for (int i = threadIdx.x; i <= span; i += NW * 64) {
+        const uint32_t off = ((static_cast<uint32_t>(mn) + static_cast<uint32_t>(i)) << 3) + L.bias;
+        const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
+        s_win[i] = make_int2(e[0], e[1]);
+      }
+      __syncthreads();
+      const uint32_t base =
+          static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(s_win)));
+      const LdsWindow Wn{base - (static_cast<uint32_t>(mn) << 3),
+                         base + (static_cast<uint32_t>(span) << 3)};
+      if (plain) {
+        for (int s = 0; s < ksteps; ++s)
+          blk_step<IT, POL, V, NW, false, true>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
+                                                led);
+      } else {
+        for (int s = 0; s < ksteps; ++s)
+          blk_step<IT, POL, V, NW, true, true>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
+                                               own_right, led);
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+    const LdsWindow Wn{0u, 0u};
+    if (plain) {
+      for (int s = 0; s < ksteps; ++s)
+        blk_step<IT, POL, V, NW, false, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
+                                               led);
+    } else {
+      for (int s = 0; s < ksteps; ++s)
+        blk_step<IT, POL, V, NW, true, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
+                                              own_right, led);
+    }
+  }
+  const int lo_t = khalo / V, hi_t = NW * 64 - khalo / V;
+  if (static_cast<int>(threadIdx.x) >= lo_t && static_cast<int>(threadIdx.x) < hi_t) {
     if (g0 + V <= n) {
       store_vec<IT, V>(dst + g0, q);
     } else {
@@ -583,6 +813,19 @@ hipError_t do_launch(int kernel, const void* src, void* dst, int64_t n, int bc, 
     if (kernel == K_TBLOCK) {
       k_tblock<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, b, n, bc, ksteps,
                                                                          khalo, ntiles, P, d_ledger);
+    } else if (kernel == K_TBLOCK_B2 || kernel == K_TBLOCK_B4 || kernel == K_TBLOCK_B8) {
+      const int nw = kernel == K_TBLOCK_B2 ? 2 : (kernel == K_TBLOCK_B4 ? 4 : 8);
+      const int64_t Tb = int64_t(nw) * 64 * V - 2 * khalo;
+      const int64_t nt = (n + Tb - 1) / Tb;
+      if (nw == 2)
+        k_tblock_blk<IT, POL, V, 2><<<dim3((unsigned)nt), dim3(128), 0, s>>>(a, b, n, bc, ksteps,
+                                                                             khalo, nt, P, d_ledger);
+      else if (nw == 4)
+        k_tblock_blk<IT, POL, V, 4><<<dim3((unsigned)nt), dim3(256), 0, s>>>(a, b, n, bc, ksteps,
+                                                                             khalo, nt, P, d_ledger);
+      else
+        k_tblock_blk<IT, POL, V, 8><<<dim3((unsigned)nt), dim3(512), 0, s>>>(a, b, n, bc, ksteps,
+                                                                             khalo, nt, P, d_ledger);
     } else {
       if constexpr (IsSplit<POL>::value) {
         k_tblock_il<IT, POL, V><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
@@ -645,11 +888,16 @@ unsigned grid_for(int64_t n, int threads) {
 
 bool scalar_variant_available(int itype, int pol, int kernel, int vec) {
   if (pol < 0 || pol >= P_COUNT) return false;
-  if (kernel != K_STREAM && kernel != K_TBLOCK && kernel != K_TBLOCK_IL) return false;
+  if (kernel < K_STREAM || kernel > K_TBLOCK_B8) return false;
   if (kernel == K_TBLOCK_IL && (pol == P_GODUNOV || pol == P_MURMAN_ROE)) return false;
   if (itype == FQNM_I32) return vec == 4 || vec == 8 || vec == 16;
   if (itype == FQNM_I64) return vec == 2 || vec == 4 || vec == 8;
   return false;
+}
+
+int scalar_tile_positions(int kernel, int vec) {
+  const int nw = kernel == K_TBLOCK_B2 ? 2 : (kernel == K_TBLOCK_B4 ? 4 : (kernel == K_TBLOCK_B8 ? 8 : 1));
+  return nw * 64 * vec;
 }
 
 int scalar_halo(int kernel, int vec, int ksteps) {
@@ -666,6 +914,9 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
   if (kernel == K_TBLOCK && (khalo < ksteps || khalo % vec != 0 || 64 * vec - 2 * khalo <= 0))
     return hipErrorInvalidValue;
   if (kernel == K_TBLOCK_IL && (khalo < ksteps || khalo % 64 != 0 || 64 * vec - 2 * khalo <= 0))
+    return hipErrorInvalidValue;
+  if (kernel >= K_TBLOCK_B2 &&
+      (khalo < ksteps || khalo % vec != 0 || scalar_tile_positions(kernel, vec) - 2 * khalo <= 0))
     return hipErrorInvalidValue;
   if (itype == FQNM_I32)
     return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);

@@ -4,7 +4,7 @@ tests run the same plans at full size."""
 from .fqnm import KERNEL_STREAM, KERNEL_TBLOCK
 
 # Burgers, 2^20 int32 cells, Engquist-Osher LUT, 10000 steps
-BENCH_PLAN_W2 = (KERNEL_TBLOCK, 8, 64)
+BENCH_PLAN_W2 = (KERNEL_TBLOCK, 4, 48)
 # near-Nyquist advection, 2^24 int64 cells, 2000 steps
 BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
 # the one-step-per-pass streaming plan reported beside it
@@ -15,7 +15,7 @@ STREAM_PLAN_W3 = (KERNEL_STREAM, 2, 1)
 # Valid only for the kernel sources they were measured on: the benchmark
 # reports null when the hash of those sources differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
-MEASURED_SOURCES_SHA = "3bc4a929a5b53294"
+MEASURED_SOURCES_SHA = "c654dcdf4b12b93c"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "w2": 11459 * 1024,  # k_tblock<int, P_LUT, 4>, 24 steps per launch
+    "w2": 11494 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
 }

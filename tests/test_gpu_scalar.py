@@ -22,10 +22,12 @@ KIND_F2O = {F.FLUX_UPWIND: O.UPWIND, F.FLUX_BURGERS_EO: O.BURGERS_EO,
 PLANS32 = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_STREAM, 16, 1),
            (F.KERNEL_TBLOCK, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 8, 8),
            (F.KERNEL_TBLOCK, 16, 32), (F.KERNEL_TBLOCK, 16, 96), (F.KERNEL_TBLOCK, 8, 64),
-           (F.KERNEL_TBLOCK_IL, 4, 16), (F.KERNEL_TBLOCK_IL, 8, 64), (F.KERNEL_TBLOCK_IL, 16, 100)]
+           (F.KERNEL_TBLOCK_IL, 4, 16), (F.KERNEL_TBLOCK_IL, 8, 64), (F.KERNEL_TBLOCK_IL, 16, 100),
+           (F.KERNEL_TBLOCK_B2, 4, 8), (F.KERNEL_TBLOCK_B4, 4, 48), (F.KERNEL_TBLOCK_B8, 8, 64)]
 PLANS64 = [(F.KERNEL_STREAM, 2, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_TBLOCK, 2, 2),
            (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48),
-           (F.KERNEL_TBLOCK_IL, 4, 8), (F.KERNEL_TBLOCK_IL, 8, 64)]
+           (F.KERNEL_TBLOCK_IL, 4, 8), (F.KERNEL_TBLOCK_IL, 8, 64),
+           (F.KERNEL_TBLOCK_B2, 2, 6), (F.KERNEL_TBLOCK_B4, 8, 24), (F.KERNEL_TBLOCK_B8, 4, 40)]
 TWO_POINT = (F.FLUX_BURGERS_GODUNOV, F.FLUX_BURGERS_MURMAN_ROE)
 
 
@@ -120,7 +122,8 @@ def test_edge_sizes(n, bc):
         q0 = O.quantise(u0, prob.delta, 32)
         for steps in (0, 1, 37):
             ref = O.step(op, q0, steps)
-            plans = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 16, 32)]
+            plans = [(F.KERNEL_STREAM, 4, 1), (F.KERNEL_TBLOCK, 4, 4), (F.KERNEL_TBLOCK, 16, 32),
+                     (F.KERNEL_TBLOCK_B4, 4, 12), (F.KERNEL_TBLOCK_B8, 8, 64)]
             if flux not in TWO_POINT:
                 plans.append((F.KERNEL_TBLOCK_IL, 4, 16))
             for plan in plans:
