@@ -110,6 +110,31 @@ def time_solver(S, steps_per_solve, K, W):
     return (t1 - t0) / K, step_s
 
 
+def bench_twin(F, W, plans, stream, int_value, reps=3):
+    """The classical split finite-volume scheme on the same Burgers workload
+    with an FP64 state (Sec. 2.1), same kernels' tiling, timed like the
+    headline (stepping only; the state is uploaded before the timer)."""
+    import torch
+    w = W.w2_burgers_step()
+    prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n)
+    ts = []
+    for _ in range(reps + 1):
+        h = F.fqnm_create_classical(prob, w.u0, stream)
+        F.fqnm_set_plan(h, *plans.TWIN_PLAN_W2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fqnm_step(h, w.steps)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        F.fqnm_destroy(h)
+    t = float(np.median(ts[1:]))
+    rate = w.n * w.steps / t
+    log(f"[bench] W2 FP64 twin {rate:.3e} cell-updates/s")
+    return {"w2_fp64_twin": {"cell_updates_per_s": rate, "ms_per_solve": t * 1e3,
+                             "plan": list(plans.TWIN_PLAN_W2),
+                             "integer_table_over_fp64": int_value / rate}}
+
+
 def bench_batch(F, W, stream, reps=3):
     """4096 instances (advection/Burgers, 256..65536 cells, 500..5000 steps) in
     one batched run against the one-instance-at-a-time loop on the same GPU."""
@@ -368,6 +393,9 @@ def main():
                     "cell_updates_per_s": rate, "ms_per_solve": sec3 * 1e3,
                     "kernel_GBps_algorithmic": ach3, "frac_of_hbm": ach3 / HBM_PEAK_GBS,
                     "frac_of_int64_roofline": rate / (HBM_PEAK_GBS * 1e9 / 16.0)}
+    # ---------------- the FP64 finite-volume twin of the headline workload ----------
+    if not args.no_extras and args.only in ("",):
+        extras.update(bench_twin(F, W, plans, stream, value))
     # ---------------- batched: 4096 independent instances --------------------------
     if not args.no_extras and args.only in ("", "batch"):
         extras.update(bench_batch(F, W, stream))

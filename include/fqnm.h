@@ -190,6 +190,20 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial);
 
 fqnm_status fqnm_destroy(fqnm_ctx* ctx); /* NULL-safe */
 
+/* The FP64 split finite-volume twin of a problem (Sec. 2.1,
+ * eq:classical_operator_definition): state u in FP64 (n doubles, u0_host is
+ * copied), the same flux kind, boundary kind and lambda, update
+ * u_i <- u_i - lambda*(F(u_i,u_{i+1}) - F(u_{i-1},u_i)) with
+ * F(uL,uR) = f+(uL) + f-(uR) (or the two-point flux), every operation one
+ * IEEE double op in a fixed order.  It exists to time the classical scheme
+ * beside the integer one on the same workload.  fqnm_step, fqnm_get_state
+ * (n doubles), fqnm_reconstruct (the state itself), plans and fqnm_destroy
+ * apply; fqnm_invariants_get returns FQNM_ERR_UNSUPPORTED.  Validation:
+ * FQNM_ERR_ARG as for fqnm_create (itype and eval are ignored, Euler kinds
+ * are refused), FQNM_ERR_CFL if lambda*max|f'| > 1 on [min u0, max u0]. */
+fqnm_status fqnm_create_classical(const fqnm_problem* prob, const double* u0_host,
+                                  void* hip_stream, fqnm_ctx** out);
+
 /* Quantise a real field on the device (Sec. 2, eq:quantisation):
  * q_host[i] = rint(u_host[i] / delta) for i < n, stored as itype.
  * FQNM_ERR_RANGE if a value does not fit the storage type (or |q| >= 2^52

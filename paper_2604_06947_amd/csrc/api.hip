@@ -410,6 +410,47 @@ fqnm_status fqnm_create_on_device(const fqnm_problem* prob, void* d_q, void* hip
   return FQNM_OK;
 }
 
+fqnm_status fqnm_create_classical(const fqnm_problem* prob, const double* u0_host,
+                                  void* hip_stream, fqnm_ctx** out) {
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(prob, hip_stream, out, &ctx);
+  if (st) return st;
+  if (!u0_host || ctx->euler) {
+    ctx_free(ctx);
+    return fail(FQNM_ERR_ARG, "u0_host is NULL, or an Euler kind (the twin is scalar)");
+  }
+  ctx->classical = true;
+  ctx->esize = 8;
+  // CFL on the range of the initial field (eq:cfl_number)
+  double umax = 0.0;
+  for (int64_t i = 0; i < prob->n; ++i) {
+    if (!std::isfinite(u0_host[i])) { ctx_free(ctx); return fail(FQNM_ERR_ARG, "u0 must be finite"); }
+    umax = std::max(umax, std::fabs(u0_host[i]));
+  }
+  double nu = 0.0;
+  if (prob->flux == FQNM_FLUX_UPWIND) nu = std::fabs(prob->a) * prob->lambda;
+  else if (prob->flux == FQNM_FLUX_LF_LINEAR || prob->flux == FQNM_FLUX_LF_BURGERS)
+    nu = prob->alpha * prob->lambda;
+  else nu = prob->lambda * umax;
+  if (nu > 1.0) { ctx_free(ctx); return fail(FQNM_ERR_CFL, "CFL number exceeds 1"); }
+  st = ctx_alloc(ctx, nullptr);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(ctx->buf[0], u0_host, ctx->state_bytes(),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) st = hip_fail(e, "copy u0");
+  }
+  if (st) { ctx_free(ctx); return st; }
+  ctx->xp = xparams_of(*prob);
+  ctx->pol = policy_of(*prob, false);
+  ctx->direct_pol = ctx->pol;
+  ctx->plan.kernel = K_TBLOCK;
+  ctx->plan.vec = 4;
+  ctx->plan.depth = 24;
+  ctx->plan.eval = FQNM_EVAL_DIRECT;
+  *out = ctx;
+  return FQNM_OK;
+}
+
 fqnm_status fqnm_destroy(fqnm_ctx* ctx) {
   if (!ctx) return FQNM_OK;
   ctx->stream_sync_on_free = true;
@@ -429,7 +470,18 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
     void* dst = buf[1 - *cur];
     int64_t k = 1;
     hipError_t e;
-    if (ctx->euler) {
+    if (ctx->classical) {
+      if (pl.kernel == K_STREAM) {
+        e = launch_classical(ctx->pol, K_STREAM, pl.vec, static_cast<const double*>(src),
+                             static_cast<double*>(dst), p.n, p.bc, 1, 0, ctx->xp, ctx->stream);
+      } else {
+        k = std::min<int64_t>(pl.depth, left);
+        const int khalo = scalar_halo(K_TBLOCK, pl.vec, static_cast<int>(k));
+        e = launch_classical(ctx->pol, K_TBLOCK, pl.vec, static_cast<const double*>(src),
+                             static_cast<double*>(dst), p.n, p.bc, static_cast<int>(k), khalo,
+                             ctx->xp, ctx->stream);
+      }
+    } else if (ctx->euler) {
       e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
                             p.bc, ctx->eparams, ctx->d_ledger, ctx->stream);
     } else if (pl.kernel == K_STREAM) {
@@ -486,6 +538,11 @@ fqnm_status fqnm_state_device(fqnm_ctx* ctx, void** d_q) {
 fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u) {
   if (!ctx || !d_u) return fail(FQNM_ERR_ARG, "NULL argument");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
+  if (ctx->classical) {
+    CTX_HIP(hipMemcpyAsync(d_u, ctx->buf[ctx->cur], ctx->state_bytes(), hipMemcpyDeviceToDevice,
+                           ctx->stream), "copy field");
+    return FQNM_OK;
+  }
   CTX_HIP(launch_reconstruct(ctx->prob.itype, ctx->buf[ctx->cur], d_u, ctx->comp * ctx->prob.n,
                              ctx->prob.delta, ctx->stream), "reconstruct");
   return FQNM_OK;
@@ -507,6 +564,7 @@ fqnm_status fqnm_reconstruct(fqnm_ctx* ctx, double* u_host) {
 
 fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
   if (!ctx || !out) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (ctx->classical) return fail(FQNM_ERR_UNSUPPORTED, "no integer invariants for the FP64 twin");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
   std::memset(out, 0, sizeof *out);
   out->components = ctx->comp;
@@ -593,7 +651,8 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
   if (plan->depth) pl.depth = plan->depth;
-  if (!scalar_variant_available(ctx->prob.itype, ctx->pol, pl.kernel, pl.vec))
+  if (ctx->classical ? !classical_variant_available(ctx->pol, pl.kernel, pl.vec)
+                     : !scalar_variant_available(ctx->prob.itype, ctx->pol, pl.kernel, pl.vec))
     return fail(FQNM_ERR_ARG, "vec not available for this storage type");
   if (pl.kernel != K_STREAM) {
     if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth must be >= 1");
@@ -608,7 +667,7 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
 fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
   if (!ctx) return fail(FQNM_ERR_ARG, "ctx is NULL");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
-  if (ctx->euler) return FQNM_OK;
+  if (ctx->euler || ctx->classical) return FQNM_OK;
   if (steps_per_trial < 1) return fail(FQNM_ERR_ARG, "steps_per_trial must be >= 1");
   const size_t bytes = ctx->state_bytes();
   void* sb[2] = {nullptr, nullptr};

@@ -153,13 +153,14 @@ __device__ __forceinline__ int dpp32(int v) {
 template <int CTRL, typename IT>
 __device__ __forceinline__ IT dpp_move(IT v) {
   if constexpr (sizeof(IT) == 4) {
-    return static_cast<IT>(dpp32<CTRL>(static_cast<int>(v)));
+    return __builtin_bit_cast(IT, dpp32<CTRL>(__builtin_bit_cast(int, v)));
   } else {
-    const uint64_t u = static_cast<uint64_t>(v);
+    // 64-bit values (integers or doubles) move as their bit patterns
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
     const int lo = dpp32<CTRL>(static_cast<int>(static_cast<uint32_t>(u)));
     const int hi = dpp32<CTRL>(static_cast<int>(static_cast<uint32_t>(u >> 32)));
-    return static_cast<IT>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
-                           static_cast<uint32_t>(lo));
+    return __builtin_bit_cast(IT, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                      static_cast<uint32_t>(lo));
   }
 }
 

@@ -41,6 +41,12 @@ bool scalar_variant_available(int itype, int pol, int kernel, int vec);
 int scalar_halo(int kernel, int vec, int ksteps);  // halo width of the temporal-blocking kernels
 int scalar_tile_positions(int kernel, int vec);     // cells loaded per tile
 
+// FP64 split finite-volume twin (state u in doubles).
+bool classical_variant_available(int pol, int kernel, int vec);
+hipError_t launch_classical(int pol, int kernel, int vec, const double* src, double* dst,
+                            int64_t n, int bc, int ksteps, int khalo, const XParams& P,
+                            hipStream_t s);
+
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
                             int64_t count, hipStream_t s);
 hipError_t launch_quantise(int itype, const double* u, void* q, int64_t n, double delta,

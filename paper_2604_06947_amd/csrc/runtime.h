@@ -11,6 +11,7 @@
 struct fqnm_ctx {
   fqnm_problem prob{};
   bool euler = false;
+  bool classical = false;  // FP64 finite-volume twin: the state holds doubles
   int comp = 1;        // components per cell
   size_t esize = 4;    // bytes per integer
   hipStream_t stream = nullptr;

@@ -35,7 +35,7 @@ KERNEL_TBLOCK_B2, KERNEL_TBLOCK_B4, KERNEL_TBLOCK_B8 = 3, 4, 5
 
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",
-    "fqnm_create_on_device", "fqnm_step", "fqnm_get_state", "fqnm_state_device",
+    "fqnm_create_on_device", "fqnm_create_classical", "fqnm_step", "fqnm_get_state", "fqnm_state_device",
     "fqnm_reconstruct", "fqnm_reconstruct_device", "fqnm_invariants_get", "fqnm_get_plan",
     "fqnm_set_plan", "fqnm_autotune", "fqnm_destroy", "fqnm_batch_create", "fqnm_batch_reset",
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
@@ -102,6 +102,7 @@ def lib():
             "fqnm_create": ([P, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_create_from_field": ([P, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_create_on_device": ([P, vp, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_create_classical": ([P, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_step": ([vp, i64], C.c_int),
             "fqnm_get_state": ([vp, vp], C.c_int),
             "fqnm_state_device": ([vp, C.POINTER(vp)], C.c_int),
@@ -180,6 +181,23 @@ def fqnm_create_from_field(prob, u0, stream=None):
     h = C.c_void_p()
     _check(lib().fqnm_create_from_field(C.byref(prob), u0.ctypes.data, stream, C.byref(h)))
     return h
+
+
+def fqnm_create_classical(prob, u0, stream=None):
+    """FP64 finite-volume twin of `prob` (state: n doubles)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).ravel()
+    if u0.size != prob.n:
+        raise ValueError("u0 has the wrong size")
+    h = C.c_void_p()
+    _check(lib().fqnm_create_classical(C.byref(prob), u0.ctypes.data, stream, C.byref(h)))
+    return h
+
+
+def fqnm_get_field(h, n):
+    """State of an FP64 twin context (n doubles)."""
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().fqnm_get_state(h, out.ctypes.data))
+    return out
 
 
 def fqnm_create_on_device(prob, d_q: int, stream=None):

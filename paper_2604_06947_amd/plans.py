@@ -19,3 +19,6 @@ MEASURED_SOURCES_SHA = "c654dcdf4b12b93c"
 TRAFFIC_BYTES_PER_LAUNCH = {
     "w2": 11494 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
 }
+
+# the FP64 finite-volume twin of the Burgers workload, same tiling machinery
+TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
