@@ -99,6 +99,8 @@ def lib():
         L.ofq_entropy.restype = C.c_double
         L.ofq_level_transitions.argtypes = [i64p, i64p, C.c_int64, i64p, i64p, i64p]
         L.ofq_level_transitions.restype = C.c_int64
+        L.ofq_row_defect.argtypes = [i64p, i64p, C.c_int64]
+        L.ofq_row_defect.restype = C.c_double
         _lib = L
     return _lib
 
@@ -243,3 +245,12 @@ def level_transitions(q0, q1):
     c = np.empty(q0.size, np.int64)
     m = lib().ofq_level_transitions(q0, q1, q0.size, f, t, c)
     return f[:m].copy(), t[:m].copy(), c[:m].copy()
+
+
+def row_defect(q0, q1) -> float:
+    """rho = max_k' |sum_k N_{k'k}/c_k - 1| over the levels occupied in q1
+    (Supplementary Information, eq:empirical_M, Remark doubly_stochastic_condition)."""
+    q0 = np.ascontiguousarray(q0, dtype=np.int64)
+    q1 = np.ascontiguousarray(q1, dtype=np.int64)
+    assert q0.size == q1.size
+    return lib().ofq_row_defect(q0, q1, q0.size)

@@ -27,7 +27,8 @@
  *   two-point rules       Sec. 2.2, eq:transfer_operator_equivalence_definition
  *   conservation          Sec. 2.3, eq:exact_conservation
  *   entropy diagnostics   Supplementary Information, eq:pk_definition,
- *                         eq:discrete_entropy, eq:empirical_M
+ *                         eq:discrete_entropy, eq:empirical_M, and the
+ *                         row-sum defect of Remark doubly_stochastic_condition
  *
  * "round" is read as IEEE round-half-to-even (C rint in the default
  * rounding mode), the rounding of the NumPy prototype the paper describes.
@@ -725,4 +726,59 @@ int64_t ofq_level_transitions(const int64_t* q0, const int64_t* q1, int64_t n, i
   }
   free(pairs);
   return m;
+}
+
+/* Row-sum defect of the empirical level-transition matrix (Supplementary
+ * Information, eq:empirical_M and Remark doubly_stochastic_condition):
+ *   M_{k'k} = N_{k'k} / c_k   (c_k = #{i : q0_i = k}),
+ *   rho = max over k' of | sum_k M_{k'k} - 1 |,
+ * with k' running over the levels occupied after the step (the rows of M that
+ * hold any entry).  Each row is summed in increasing k.  Returns -1.0 on
+ * allocation failure and 0.0 for n == 0. */
+static int cmp_pair_rev(const void* a, const void* b) {
+  const int64_t* x = (const int64_t*)a;
+  const int64_t* y = (const int64_t*)b;
+  if (x[1] != y[1]) return (x[1] > y[1]) - (x[1] < y[1]);
+  return (x[0] > y[0]) - (x[0] < y[0]);
+}
+
+double ofq_row_defect(const int64_t* q0, const int64_t* q1, int64_t n) {
+  if (n == 0) return 0.0;
+  int64_t* lv = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* ct = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* f = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* t = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* c = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* trip = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)n);
+  double rho = -1.0;
+  if (!lv || !ct || !f || !t || !c || !trip) goto done;
+  {
+    const int64_t nl = ofq_level_histogram(q0, n, lv, ct);
+    const int64_t m = ofq_level_transitions(q0, q1, n, f, t, c);
+    /* triples (k, k', N) ordered by (k', k) */
+    for (int64_t r = 0; r < m; ++r) {
+      trip[3 * r] = f[r];
+      trip[3 * r + 1] = t[r];
+      trip[3 * r + 2] = c[r];
+    }
+    qsort(trip, (size_t)m, 3 * sizeof(int64_t), cmp_pair_rev);
+    rho = 0.0;
+    int64_t r = 0;
+    while (r < m) {
+      const int64_t kp = trip[3 * r + 1];
+      double row = 0.0;
+      for (; r < m && trip[3 * r + 1] == kp; ++r) {
+        /* c_k by lookup in the (sorted) histogram of q0 */
+        const int64_t* hit =
+            (const int64_t*)bsearch(&trip[3 * r], lv, (size_t)nl, sizeof(int64_t), cmp_i64);
+        const int64_t ck = ct[hit - lv];
+        row += (double)trip[3 * r + 2] / (double)ck;
+      }
+      const double d = fabs(row - 1.0);
+      if (d > rho) rho = d;
+    }
+  }
+done:
+  free(lv); free(ct); free(f); free(t); free(c); free(trip);
+  return rho;
 }

@@ -541,6 +541,63 @@ def test_level_transition_counts_are_consistent():
     assert c.sum() == q1.size
 
 
+def test_row_defect_hand_examples():
+    # [0,0,1] -> [1,0,0]: N_00 = N_10 = N_01 = 1, c_0 = 2, c_1 = 1, so
+    # row 0 sums to 1/2 + 1 and row 1 to 1/2: rho = 1/2 (worked by hand)
+    assert O.row_defect([0, 0, 1], [1, 0, 0]) == 0.5
+    # [0,1] -> [1,1]: level 0 empties, row 1 = 1/1 + 1/1 = 2
+    assert O.row_defect([0, 1], [1, 1]) == 1.0
+    # identity, a shift of every level, and an even mixing of two equal levels
+    # are doubly stochastic
+    q = np.array([3, -1, 3, 0, 0, 0, 7])
+    assert O.row_defect(q, q) == 0.0
+    assert O.row_defect(q, q + 7) == 0.0
+    assert O.row_defect([0, 0, 1, 1], [0, 1, 0, 1]) == 0.0
+    assert O.row_defect([], []) == 0.0
+
+
+def _dense_transition_matrix(q0, q1):
+    """Brute force: M as a dense matrix over the union of levels, one cell at a time."""
+    lv = sorted(set(int(x) for x in q0) | set(int(x) for x in q1))
+    ix = {k: j for j, k in enumerate(lv)}
+    N = np.zeros((len(lv), len(lv)))
+    for a, b in zip(q0, q1):
+        N[ix[int(b)], ix[int(a)]] += 1
+    c0 = np.array([sum(1 for a in q0 if a == k) for k in lv], dtype=float)
+    M = np.divide(N, c0[None, :], out=np.zeros_like(N), where=c0[None, :] > 0)
+    return lv, M, c0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_row_defect_matches_dense_matrix(seed):
+    rng = np.random.default_rng(seed)
+    n = 40
+    q0 = rng.integers(-3, 4, n)
+    q1 = q0 + rng.integers(-1, 2, n)
+    lv, M, c0 = _dense_transition_matrix(q0, q1)
+    p0 = c0 / n
+    p1 = np.array([sum(1 for b in q1 if b == k) for k in lv], dtype=float) / n
+    # eq:pn1_equals_Mpn and column-stochasticity on the occupied levels
+    assert np.allclose(M @ p0, p1, atol=1e-15)
+    assert np.allclose(M.sum(axis=0)[c0 > 0], 1.0, atol=1e-15)
+    rows = M.sum(axis=1)[p1 > 0]
+    assert abs(O.row_defect(q0, q1) - np.abs(rows - 1.0).max()) < 1e-14
+    # the entries of M add up to the number of levels occupied before the step
+    assert abs(rows.sum() - np.count_nonzero(c0)) < 1e-12
+
+
+def test_row_defect_zero_implies_entropy_does_not_drop():
+    # equal level counts permuted among cells: M is doubly stochastic
+    # (Remark doubly_stochastic_condition) and the entropy cannot decrease
+    # (Theorem entropy_increase); here it is unchanged
+    rng = np.random.default_rng(5)
+    q0 = np.repeat(np.arange(-5, 6), 9)
+    q1 = rng.permutation(q0)
+    # each row is a sum of ninths that add up to one, up to rounding
+    assert O.row_defect(q0, q1) < 4e-16
+    assert O.entropy(q1) >= O.entropy(q0) - 1e-15
+
+
 # Transonic rarefactions (left-going, and its mirror image right-going): plain
 # Roe admits an entropy-violating expansion jump at the sonic point, and the
 # entropy fix of the acoustic waves removes it, so against the exact solution
