@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve")
+    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels")
     return ap.parse_args()
 
 
@@ -266,6 +266,48 @@ def bench_serve(F, W, stream):
     return res
 
 
+def bench_levels(F, W, stream, reps=5):
+    """Level statistics at the headline size (2^20 int32 cells, Burgers EO after
+    2000 steps): histogram + entropy, and one transition step with its counts
+    and row-sum defect.  Wall clock per call (device sort, host sums, copies
+    and the per-call temporary allocations included); the oracle's entropy and
+    transition counts on the same state are timed beside it."""
+    import oracle as O
+    w = W.w2_burgers_step()
+    prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32, eval_=F.EVAL_LUT)
+    h = F.fqnm_create_from_field(prob, w.u0, stream)
+    try:
+        F.fqnm_step(h, 2000)
+        q = F.fqnm_get_state(h, prob).astype(np.int64)
+        F.fqnm_entropy(h)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            S, _ = F.fqnm_entropy(h)
+        t_ent = (time.perf_counter() - t0) / reps
+        nl = F.fqnm_level_histogram(h)[0].size
+        F.fqnm_step_transitions(h, w.n)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, c, rho = F.fqnm_step_transitions(h, w.n)
+        t_tr = (time.perf_counter() - t0) / reps
+    finally:
+        F.fqnm_destroy(h)
+    t0 = time.perf_counter()
+    O.entropy(q)
+    t_ent_cpu = time.perf_counter() - t0
+    q1 = q.copy()
+    t0 = time.perf_counter()
+    O.level_transitions(q, q1)
+    O.row_defect(q, q1)
+    t_tr_cpu = time.perf_counter() - t0
+    return {"levels_w2": {
+        "cells": w.n, "occupied_levels": int(nl), "entropy": S, "transition_pairs": int(c.size),
+        "row_defect": rho,
+        "entropy_ms": t_ent * 1e3, "entropy_cells_per_s": w.n / t_ent,
+        "transitions_ms": t_tr * 1e3, "transitions_cells_per_s": w.n / t_tr,
+        "oracle_entropy_ms": t_ent_cpu * 1e3, "oracle_transitions_ms": t_tr_cpu * 1e3}}
+
+
 def cpu_oracle_rate(w, steps):
     import oracle as O
     op = O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32)
@@ -304,6 +346,8 @@ def run_extras_only(args, F, W, plans, stream):
         extras.update(bench_batch(F, W, stream))
     elif args.only == "serve":
         extras.update(bench_serve(F, W, stream))
+    elif args.only == "levels":
+        extras.update(bench_levels(F, W, stream))
     print(json.dumps({"extras": extras}), flush=True)
 
 
@@ -402,6 +446,9 @@ def main():
     # ---------------- served: Sod requests with Poisson arrivals -----------------------
     if not args.no_extras and args.only in ("", "serve"):
         extras.update(bench_serve(F, W, stream))
+    # ---------------- level statistics (entropy, transitions) -------------------------
+    if not args.no_extras and args.only in ("", "levels"):
+        extras.update(bench_levels(F, W, stream))
     # ---------------- CPU oracle baseline --------------------------------------------
     if not args.no_cpu:
         csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "600"))

@@ -219,6 +219,40 @@ fqnm_status fqnm_fp64_selfcheck(const double* d_a, const double* d_b, double* d_
                                 double* d_out_div, int64_t n, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Level statistics of a scalar integer state (Supplementary Information).
+ * c_k = #{i : q_i = k} and p_k = c_k / n (eq:pk_definition); these calls are
+ * diagnostics, computed on the device by a radix sort of the state and a
+ * run-length encoding, with temporary device memory allocated per call.  They
+ * synchronise the context's stream.  FQNM_ERR_UNSUPPORTED for Euler and FP64
+ * twin contexts and for n > 2^31 - 1.
+ * ---------------------------------------------------------------------- */
+
+/* Occupied levels of the current state in increasing order, with their
+ * counts: levels[j], counts[j] for j < min(cap, *n_levels).  *n_levels
+ * receives the number of occupied levels even when it exceeds cap (cap = 0
+ * with NULL arrays asks for the count only).  FQNM_ERR_ARG for NULL
+ * n_levels, cap < 0, or cap > 0 with a NULL array. */
+fqnm_status fqnm_level_histogram(fqnm_ctx* ctx, int64_t* levels, int64_t* counts, int64_t cap,
+                                 int64_t* n_levels);
+
+/* Discrete entropy S = -sum_k p_k log p_k of the current state
+ * (eq:discrete_entropy), summed over the occupied levels in increasing level
+ * order, and N_eff = exp(S) (eq:neff) if n_eff is non-NULL. */
+fqnm_status fqnm_entropy(fqnm_ctx* ctx, double* S, double* n_eff);
+
+/* Advance the context by ONE step and report the level-transition counts of
+ * that step (Definition level_transition): N_{k'k} = #{i : q_i^n = k and
+ * q_i^{n+1} = k'} as triples (from[j] = k, to[j] = k', count[j] = N_{k'k}),
+ * the nonzero ones, in increasing (k, k') order, for j < min(cap, *n_pairs).
+ * *n_pairs receives the number of nonzero triples.  If row_defect is
+ * non-NULL it receives rho = max over k' of |sum_k N_{k'k} / c_k^n - 1|
+ * (eq:empirical_M, Remark doubly_stochastic_condition), k' running over the
+ * levels occupied after the step, each row summed in increasing k.  The step
+ * is the context's ordinary step (counted in its step total). */
+fqnm_status fqnm_step_transitions(fqnm_ctx* ctx, int64_t* from, int64_t* to, int64_t* count,
+                                  int64_t cap, int64_t* n_pairs, double* row_defect);
+
+/* ------------------------------------------------------------------------
  * Batching: many independent instances (each its own problem, state and step
  * count) advanced together.  Instances that fit one workgroup run every one
  * of their steps inside one persistent launch with their state held in

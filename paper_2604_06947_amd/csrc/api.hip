@@ -253,11 +253,12 @@ static void ctx_free(fqnm_ctx* ctx) {
   if (ctx->d_u) (void)hipFree(ctx->d_u);
   if (ctx->d_red) (void)hipFree(ctx->d_red);
   if (ctx->d_err) (void)hipFree(ctx->d_err);
+  if (ctx->d_ws) (void)hipFree(ctx->d_ws);
   delete ctx;
 }
 
 // Range of component 0 of the current state via the device reduction.
-static fqnm_status device_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi) {
+fqnm_status fqnm::ctx_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi) {
   const int64_t nb = reduce_blocks(ctx->prob.n);
   if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
     return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
@@ -284,7 +285,7 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
   if (ctx->euler) {
     for (int c = 0; c < 3; ++c) {
       int64_t lo, hi;
-      fqnm_status st = device_minmax(ctx, c, &lo, &hi);
+      fqnm_status st = ctx_minmax(ctx, c, &lo, &hi);
       if (st) return st;
       st = validate_range(p, lo, hi);
       if (st) return st;
@@ -297,7 +298,7 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     return FQNM_OK;
   }
   int64_t lo, hi;
-  fqnm_status st = device_minmax(ctx, 0, &lo, &hi);
+  fqnm_status st = ctx_minmax(ctx, 0, &lo, &hi);
   if (st) return st;
   st = validate_range(p, lo, hi);
   if (st) return st;

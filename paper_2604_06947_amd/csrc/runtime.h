@@ -32,6 +32,8 @@ struct fqnm_ctx {
   int64_t q0min = 0, q0max = 0;
   bool poisoned = false;
   bool stream_sync_on_free = false;
+  void* d_ws = nullptr;  // diagnostics workspace, grown on demand, freed with the context
+  size_t ws_bytes = 0;
 
   size_t state_bytes() const { return static_cast<size_t>(comp) * prob.n * esize; }
 };
@@ -51,6 +53,9 @@ fqnm_plan default_plan(const fqnm_problem& p);
 std::string plan_key(const fqnm_problem& p, int pol);
 bool lookup_plan(const std::string& key, fqnm_plan* out);
 void store_plan(const std::string& key, const fqnm_plan& pl);
+
+// Range of component comp of the current state (device reduction, syncs).
+fqnm_status ctx_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi);
 
 // Enqueue n_steps of the context's problem from buf[*cur] with plan pl,
 // flipping *cur once per launch.

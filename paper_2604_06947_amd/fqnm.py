@@ -41,6 +41,7 @@ EXPORTED = [
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
     "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
     "fqnm_server_drain", "fqnm_server_stats_get", "fqnm_server_now", "fqnm_server_destroy",
+    "fqnm_level_histogram", "fqnm_entropy", "fqnm_step_transitions",
 ]
 
 
@@ -129,6 +130,10 @@ def lib():
             "fqnm_fp64_selfcheck": ([vp, vp, vp, vp, i64, vp], C.c_int),
             "fqnm_quantise": ([vp, i64, C.c_double, i32, vp, vp], C.c_int),
             "fqnm_server_destroy": ([vp], C.c_int),
+            "fqnm_level_histogram": ([vp, vp, vp, i64, C.POINTER(i64)], C.c_int),
+            "fqnm_entropy": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+            "fqnm_step_transitions": ([vp, vp, vp, vp, i64, C.POINTER(i64),
+                                       C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -278,6 +283,39 @@ def fqnm_quantise(u, delta, itype, stream=None):
 def fqnm_fp64_selfcheck(d_a: int, d_b: int, d_sqrt: int, d_div: int, n: int, stream=None):
     _check(lib().fqnm_fp64_selfcheck(C.c_void_p(d_a), C.c_void_p(d_b), C.c_void_p(d_sqrt),
                                      C.c_void_p(d_div), int(n), stream))
+
+
+# --------------------------------------------------------------------------
+# level statistics (Supplementary Information)
+# --------------------------------------------------------------------------
+def fqnm_level_histogram(h):
+    """Occupied levels of the current state and their counts (eq:pk_definition)."""
+    m = C.c_int64(0)
+    _check(lib().fqnm_level_histogram(h, None, None, 0, C.byref(m)))
+    lv = np.empty(max(m.value, 1), np.int64)
+    ct = np.empty(max(m.value, 1), np.int64)
+    _check(lib().fqnm_level_histogram(h, lv.ctypes.data, ct.ctypes.data, m.value, C.byref(m)))
+    return lv[:m.value], ct[:m.value]
+
+
+def fqnm_entropy(h):
+    """(S, N_eff) of the current state (eq:discrete_entropy, eq:neff)."""
+    S, neff = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().fqnm_entropy(h, C.byref(S), C.byref(neff)))
+    return S.value, neff.value
+
+
+def fqnm_step_transitions(h, n):
+    """Advance one step; return (from, to, count, row_defect) of that step
+    (Definition level_transition, Remark doubly_stochastic_condition)."""
+    cap = max(int(n), 1)
+    f = np.empty(cap, np.int64)
+    t = np.empty(cap, np.int64)
+    c = np.empty(cap, np.int64)
+    m, rho = C.c_int64(0), C.c_double(0.0)
+    _check(lib().fqnm_step_transitions(h, f.ctypes.data, t.ctypes.data, c.ctypes.data, cap,
+                                       C.byref(m), C.byref(rho)))
+    return f[:m.value], t[:m.value], c[:m.value], rho.value
 
 
 # --------------------------------------------------------------------------
