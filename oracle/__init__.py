@@ -99,6 +99,9 @@ def lib():
         L.ofq_entropy.restype = C.c_double
         L.ofq_level_transitions.argtypes = [i64p, i64p, C.c_int64, i64p, i64p, i64p]
         L.ofq_level_transitions.restype = C.c_int64
+        L.ofq_step_nd.argtypes = [C.POINTER(_Problem), C.c_int32, i64p, i64p, C.c_int64,
+                                  C.POINTER(C.c_int64)]
+        L.ofq_step_nd.restype = C.c_int
         L.ofq_row_defect.argtypes = [i64p, i64p, C.c_int64]
         L.ofq_row_defect.restype = C.c_double
         _lib = L
@@ -144,6 +147,24 @@ def step(prob: Problem, q, nsteps, return_ledger=False):
     q = np.array(q, dtype=np.int64, copy=True)
     led = C.c_int64(0)
     _check(lib().ofq_step(C.byref(prob.c()), q.size, q, int(nsteps), C.byref(led)))
+    return (q, led.value) if return_ledger else q
+
+
+def step_nd(axes, q, nsteps, return_ledger=False):
+    """d-dimensional directional composition (Thm dimension_extension).
+
+    ``q`` is a C-ordered array whose LAST numpy axis is the contiguous one;
+    ``axes[m]`` is the Problem of direction m, with ``axes[0]`` for that last
+    numpy axis, ``axes[1]`` for the one before it, and so on."""
+    q = np.array(q, dtype=np.int64, copy=True, order="C")
+    dim = q.ndim
+    assert len(axes) == dim and 1 <= dim <= 3
+    shape = np.array(q.shape[::-1], dtype=np.int64)
+    arr = (_Problem * dim)(*[a.c() for a in axes])
+    led = C.c_int64(0)
+    flat = q.reshape(-1)
+    _check(lib().ofq_step_nd(arr, dim, shape, flat, int(nsteps), C.byref(led)))
+    q = flat.reshape(q.shape)
     return (q, led.value) if return_ledger else q
 
 
