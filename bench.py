@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels")
+    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels, nd")
     return ap.parse_args()
 
 
@@ -266,6 +266,45 @@ def bench_serve(F, W, stream):
     return res
 
 
+def bench_nd(F, W, plans, stream, reps=3):
+    """W6: 2-D Burgers by directional composition, 4096 x 4096 int32 cells,
+    1000 steps, one step per launch of the marching kernel; device time of
+    the whole solve by HIP events on the library's stream (the state is
+    uploaded before the timer)."""
+    import torch
+    w = W.w6_burgers_2d()
+    ny, nx = w.shape
+    q0 = F.fqnm_quantise(w.u0.ravel(), w.delta, F.I32, stream).reshape(w.shape)
+    axes = [F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam[m], (nx, ny)[m], itype=F.I32)
+            for m in range(2)]
+    ts = []
+    for _ in range(reps + 1):
+        h = F.fqnm_create_nd(axes, q0, stream)
+        F.fqnm_set_plan(h, F.KERNEL_ND_MARCH, *plans.ND_PLAN_W6)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        F.fqnm_step(h, w.steps)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+        inv = F.fqnm_invariants_get(h)
+        F.fqnm_destroy(h)
+    t = float(np.median(ts[1:]))
+    cells = nx * ny
+    rate = cells * w.steps / t
+    ach = 8.0 * cells / (t / w.steps) / 1e9
+    log(f"[bench] W6 2-D {rate:.3e} cell-updates/s, {ach:.0f} GB/s algorithmic")
+    return {"w6_burgers_2d": {
+        "cells": cells, "shape": [ny, nx], "time_steps": w.steps, "cell_updates_per_s": rate,
+        "ms_per_solve": t * 1e3, "plan": list(plans.ND_PLAN_W6),
+        "kernel": "k_nd_march<int, P_EO, %d, 2>" % plans.ND_PLAN_W6[0],
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "bytes_per_cell_update": 8,
+                     "avg_launch_us": t / w.steps * 1e6},
+        "conservation_ok": inv["sum"][0] == int(q0.astype(np.int64).sum())}}
+
+
 def bench_levels(F, W, stream, reps=5):
     """Level statistics at the headline size (2^20 int32 cells, Burgers EO after
     2000 steps): histogram + entropy, and one transition step with its counts
@@ -348,6 +387,8 @@ def run_extras_only(args, F, W, plans, stream):
         extras.update(bench_serve(F, W, stream))
     elif args.only == "levels":
         extras.update(bench_levels(F, W, stream))
+    elif args.only == "nd":
+        extras.update(bench_nd(F, W, plans, stream))
     print(json.dumps({"extras": extras}), flush=True)
 
 
@@ -446,6 +487,9 @@ def main():
     # ---------------- served: Sod requests with Poisson arrivals -----------------------
     if not args.no_extras and args.only in ("", "serve"):
         extras.update(bench_serve(F, W, stream))
+    # ---------------- 2-D directional composition -------------------------------------
+    if not args.no_extras and args.only in ("", "nd"):
+        extras.update(bench_nd(F, W, plans, stream))
     # ---------------- level statistics (entropy, transitions) -------------------------
     if not args.no_extras and args.only in ("", "levels"):
         extras.update(bench_levels(F, W, stream))

@@ -113,11 +113,12 @@ typedef struct {
   uint64_t sum_lo[3];
   int64_t qmin[3];
   int64_t qmax[3];
-  int64_t tv_hi[3];     /* sum_i |q_{i+1} - q_i| (periodic: including the wrap term)     */
+  int64_t tv_hi[3];     /* sum_i |q_{i+1} - q_i| (periodic: including the wrap term);
+                           0 for d-D contexts                                            */
   uint64_t tv_lo[3];
   int64_t ledger[3];    /* outflow: sum over steps of F_{-1/2} - F_{n-1/2}, the net count
-                           that entered through the boundaries; periodic: 0.  Invariant:
-                           sum(q) - sum(q0) == ledger                                    */
+                           that entered through the boundaries (d-D: over every outflow
+                           face); periodic: 0.  Invariant: sum(q) - sum(q0) == ledger    */
 } fqnm_invariants;
 
 /* Launch plan of the single-grid stepper.  kernel 0 = one step per pass
@@ -125,7 +126,11 @@ typedef struct {
  * consecutive cells in registers (vec consecutive cells per lane) and
  * advances it `depth` steps per pass over memory; 2 = temporal blocking with
  * lane-interleaved cells (consecutive cells in consecutive lanes, so table
- * reads coalesce), split kinds only.  Zero fields mean "keep". */
+ * reads coalesce), split kinds only; 3, 4, 5 = temporal blocking in
+ * workgroup tiles of 2, 4 or 8 wavefronts; 6 = the d-D marching kernel (the
+ * only one of d-D contexts): a wavefront owns 64*vec cells of axis 0 and
+ * marches `depth` cells along the last axis, one step per pass.  Zero fields
+ * mean "keep". */
 typedef struct {
   int32_t kernel;
   int32_t vec;          /* cells per lane                                                */
@@ -203,6 +208,28 @@ fqnm_status fqnm_destroy(fqnm_ctx* ctx); /* NULL-safe */
  * are refused), FQNM_ERR_CFL if lambda*max|f'| > 1 on [min u0, max u0]. */
 fqnm_status fqnm_create_classical(const fqnm_problem* prob, const double* u0_host,
                                   void* hip_stream, fqnm_ctx** out);
+
+/* A d-dimensional Cartesian grid, d = 2 or 3, advanced by directional
+ * composition (Thm dimension_extension, eq:nd_transfer_rule,
+ * eq:nd_flux_definition): each step every cell subtracts, for every direction
+ * m, the difference of the one-dimensional transfers across its two faces
+ * orthogonal to m, all evaluated from the state before the step.  axes[m]
+ * describes direction m: n = cells along the axis, bc, a, alpha, lambda
+ * (= dt/dx_m) and dx; flux, itype and delta must be the same on every axis.
+ * Axis 0 is contiguous: cell (i_0, .., i_{d-1}) is element
+ * i_0 + n_0*(i_1 + n_1*i_2) of q0_host (prod n_m values of itype, copied).
+ * Outflow ends copy the cell into its ghost, per direction.  The single-grid
+ * calls (step, get/state, reconstruct, invariants, plans, autotune, level
+ * statistics, destroy) apply with n = prod n_m.  Errors: FQNM_ERR_ARG for a
+ * bad dim, an invalid axis, axes that disagree, more than 2^36 cells, or
+ * an axis of 2^31 cells or more;
+ * FQNM_ERR_UNSUPPORTED for Euler kinds and for eval = FQNM_EVAL_LUT (the
+ * composed rounding keeps no exact maximum principle, on which the table
+ * range rests); FQNM_ERR_CFL if the CFL numbers of the directions add up to
+ * more than 1; FQNM_ERR_RANGE if states or transfers could overflow (int32
+ * keeps a margin of 2^24 counts). */
+fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0_host,
+                           void* hip_stream, fqnm_ctx** out);
 
 /* Quantise a real field on the device (Sec. 2, eq:quantisation):
  * q_host[i] = rint(u_host[i] / delta) for i < n, stored as itype.

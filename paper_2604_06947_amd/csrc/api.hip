@@ -111,35 +111,70 @@ static double map_bound(const fqnm_problem& p, int64_t lo, int64_t hi) {
   }
 }
 
+// CFL number of one direction on the state range (Sec. 2.2, eq:cfl_number):
+// nu = dt/dx * max|f'| over |q| <= qa.
+static fqnm_status cfl_number(const fqnm_problem& p, double qa, double* nu) {
+  *nu = 0.0;
+  switch (p.flux) {
+    case FQNM_FLUX_UPWIND: *nu = std::fabs(p.a) * p.lambda; break;
+    case FQNM_FLUX_BURGERS_EO:
+    case FQNM_FLUX_BURGERS_GODUNOV:
+    case FQNM_FLUX_BURGERS_MURMAN_ROE: *nu = p.lambda * (p.delta * qa); break;
+    case FQNM_FLUX_LF_LINEAR:
+      if (p.alpha < std::fabs(p.a)) return fail(FQNM_ERR_CFL, "LF needs alpha >= |a|");
+      *nu = p.alpha * p.lambda;
+      break;
+    case FQNM_FLUX_LF_BURGERS:
+      if (p.alpha < p.delta * qa) return fail(FQNM_ERR_CFL, "LF needs alpha >= max|u|");
+      *nu = p.alpha * p.lambda;
+      break;
+  }
+  return FQNM_OK;
+}
+
+static fqnm_status cfl_fail(double nu) {
+  char b[128];
+  std::snprintf(b, sizeof b, "CFL number %.6g exceeds 1", nu);
+  return fail(FQNM_ERR_CFL, b);
+}
+
 fqnm_status validate_range(const fqnm_problem& p, int64_t lo, int64_t hi) {
   const double qa = std::max(std::fabs((double)lo), std::fabs((double)hi));
   if (qa >= 4503599627370496.0) return fail(FQNM_ERR_RANGE, "|q| must stay below 2^52");
   if (is_euler(p.flux)) return FQNM_OK;
   if (is_burgers(p.flux) && qa > 94906265.0)
     return fail(FQNM_ERR_RANGE, "Burgers kinds need q^2 < 2^53 (|q| <= 94906265)");
-  // CFL (Sec. 2.2, eq:cfl_number): nu = dt/dx * max|f'| <= 1 on the state range.
   double nu = 0.0;
-  switch (p.flux) {
-    case FQNM_FLUX_UPWIND: nu = std::fabs(p.a) * p.lambda; break;
-    case FQNM_FLUX_BURGERS_EO:
-    case FQNM_FLUX_BURGERS_GODUNOV:
-    case FQNM_FLUX_BURGERS_MURMAN_ROE: nu = p.lambda * (p.delta * qa); break;
-    case FQNM_FLUX_LF_LINEAR:
-      if (p.alpha < std::fabs(p.a)) return fail(FQNM_ERR_CFL, "LF needs alpha >= |a|");
-      nu = p.alpha * p.lambda;
-      break;
-    case FQNM_FLUX_LF_BURGERS:
-      if (p.alpha < p.delta * qa) return fail(FQNM_ERR_CFL, "LF needs alpha >= max|u|");
-      nu = p.alpha * p.lambda;
-      break;
-  }
-  if (nu > 1.0) {
-    char b[128];
-    std::snprintf(b, sizeof b, "CFL number %.6g exceeds 1", nu);
-    return fail(FQNM_ERR_CFL, b);
-  }
+  fqnm_status st = cfl_number(p, qa, &nu);
+  if (st) return st;
+  if (nu > 1.0) return cfl_fail(nu);
   const double lim = p.itype == FQNM_I32 ? 2147483647.0 : 4611686018427387904.0;
   if (qa + 2.0 * map_bound(p, lo, hi) >= lim)
+    return fail(FQNM_ERR_RANGE, "states or transfers would overflow the storage type");
+  return FQNM_OK;
+}
+
+// d-D (Thm dimension_extension): the summed CFL number of the directions must
+// not exceed 1.  The composed quantised update has no exact maximum principle
+// (rounding steps of several directions can add up), so int32 states keep a
+// margin of 2^24 counts below the storage limit.
+static fqnm_status validate_nd_range(const fqnm_problem* axes, int dim, int64_t lo, int64_t hi) {
+  const double qa = std::max(std::fabs((double)lo), std::fabs((double)hi));
+  const fqnm_problem& p = axes[0];
+  if (qa >= 4503599627370496.0) return fail(FQNM_ERR_RANGE, "|q| must stay below 2^52");
+  if (is_burgers(p.flux) && qa > 94906265.0)
+    return fail(FQNM_ERR_RANGE, "Burgers kinds need q^2 < 2^53 (|q| <= 94906265)");
+  double nu = 0.0, bound = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    double num = 0.0;
+    fqnm_status st = cfl_number(axes[m], qa, &num);
+    if (st) return st;
+    nu += num;
+    bound += 2.0 * map_bound(axes[m], lo, hi);
+  }
+  if (nu > 1.0) return cfl_fail(nu);
+  const double lim = p.itype == FQNM_I32 ? 2147483647.0 - 16777216.0 : 4611686018427387904.0;
+  if (qa + bound >= lim)
     return fail(FQNM_ERR_RANGE, "states or transfers would overflow the storage type");
   return FQNM_OK;
 }
@@ -343,6 +378,18 @@ static fqnm_status ctx_new(const fqnm_problem* prob, void* stream, fqnm_ctx** ou
   return FQNM_OK;
 }
 
+// Plan-cache key of a d-D context: dimension, kind, storage and the log2 of
+// each extent.
+static std::string nd_plan_key(const fqnm_ctx* ctx) {
+  std::string k = "nd" + std::to_string(ctx->dim) + "_" + plan_key(ctx->prob, ctx->pol);
+  for (int m = 0; m < ctx->dim; ++m) {
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= ctx->nd.ax[m].n) ++lg;
+    k += "_" + std::to_string(lg);
+  }
+  return k;
+}
+
 extern "C" {
 
 const char* fqnm_last_error(void) { return tl_error.c_str(); }
@@ -407,6 +454,66 @@ fqnm_status fqnm_create_on_device(const fqnm_problem* prob, void* d_q, void* hip
   st = ctx_alloc(ctx, d_q);
   if (!st) st = ctx_finish(ctx);
   if (st) { ctx_free(ctx); return st; }
+  *out = ctx;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0_host,
+                           void* hip_stream, fqnm_ctx** out) {
+  if (!out) return fail(FQNM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!axes || !q0_host) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(FQNM_ERR_ARG, "dim must be 2 or 3");
+  int64_t total = 1;
+  for (int m = 0; m < dim; ++m) {
+    fqnm_status st = validate_problem(&axes[m]);
+    if (st) return st;
+    if (is_euler(axes[m].flux)) return fail(FQNM_ERR_UNSUPPORTED, "d-D grids take scalar kinds");
+    if (axes[m].flux != axes[0].flux || axes[m].itype != axes[0].itype ||
+        axes[m].delta != axes[0].delta)
+      return fail(FQNM_ERR_ARG, "all axes must share flux kind, itype and delta");
+    if (axes[m].eval == FQNM_EVAL_LUT)
+      return fail(FQNM_ERR_UNSUPPORTED,
+                  "no LUT mode in d-D: its table range rests on a maximum principle");
+    if (axes[m].n > INT32_MAX) return fail(FQNM_ERR_ARG, "an axis holds more than 2^31 - 1 cells");
+    if (total > (int64_t(1) << 36) / axes[m].n) return fail(FQNM_ERR_ARG, "grid too large");
+    total *= axes[m].n;
+  }
+  fqnm_problem p0 = axes[0];
+  p0.n = total;
+  p0.eval = FQNM_EVAL_DIRECT;
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(&p0, hip_stream, out, &ctx);
+  if (st) return st;
+  ctx->dim = dim;
+  ctx->nd.dim = dim;
+  for (int m = 0; m < dim; ++m) {
+    NdAxis& A = ctx->nd.ax[m];
+    A.x = xparams_of(axes[m]);
+    A.cp = A.x.c > 0.0 ? A.x.c : 0.0;
+    A.cm = A.x.c < 0.0 ? A.x.c : 0.0;
+    A.n = axes[m].n;
+    A.bc = axes[m].bc;
+  }
+  st = ctx_alloc(ctx, nullptr);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(ctx->buf[0], q0_host, ctx->state_bytes(),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) st = hip_fail(e, "copy q0");
+  }
+  int64_t lo = 0, hi = 0;
+  if (!st) st = ctx_minmax(ctx, 0, &lo, &hi);
+  if (!st) st = validate_nd_range(axes, dim, lo, hi);
+  if (st) { ctx_free(ctx); return st; }
+  ctx->q0min = lo;
+  ctx->q0max = hi;
+  ctx->xp = ctx->nd.ax[0].x;
+  ctx->pol = p0.flux == FQNM_FLUX_UPWIND ? P_UPWIND_POS : policy_of(p0, false);
+  ctx->direct_pol = ctx->pol;
+  fqnm_plan pl{K_ND_MARCH, p0.itype == FQNM_I32 ? 4 : 2, 16, FQNM_EVAL_DIRECT};
+  fqnm_plan cached;
+  if (lookup_plan(nd_plan_key(ctx), &cached)) pl = cached;
+  ctx->plan = pl;
   *out = ctx;
   return FQNM_OK;
 }
@@ -482,6 +589,9 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
                              static_cast<double*>(dst), p.n, p.bc, static_cast<int>(k), khalo,
                              ctx->xp, ctx->stream);
       }
+    } else if (ctx->dim > 1) {
+      e = launch_nd(p.itype, ctx->pol, pl.vec, pl.depth, src, dst, ctx->nd, ctx->d_ledger,
+                    ctx->stream);
     } else if (ctx->euler) {
       e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
                             p.bc, ctx->eparams, ctx->d_ledger, ctx->stream);
@@ -592,6 +702,7 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
     }
     out->sum_hi[c] = static_cast<int64_t>(s >> 64);
     out->sum_lo[c] = static_cast<uint64_t>(s);
+    if (ctx->dim > 1) tv = 0;  // the 1-D total variation of the flat array means nothing in d-D
     out->tv_hi[c] = static_cast<int64_t>(tv >> 64);
     out->tv_lo[c] = static_cast<uint64_t>(tv);
     out->qmin[c] = lo;
@@ -648,6 +759,17 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (!ctx || !plan) return fail(FQNM_ERR_ARG, "NULL argument");
   if (ctx->euler) return fail(FQNM_ERR_UNSUPPORTED, "Euler contexts have a fixed plan");
   fqnm_plan pl = ctx->plan;
+  if (ctx->dim > 1) {
+    if (plan->kernel != 0 && plan->kernel != K_ND_MARCH)
+      return fail(FQNM_ERR_ARG, "d-D contexts run the marching kernel only");
+    if (plan->vec) pl.vec = plan->vec;
+    if (plan->depth) pl.depth = plan->depth;
+    if (!nd_variant_available(ctx->prob.itype, ctx->pol, pl.vec))
+      return fail(FQNM_ERR_ARG, "vec not available for this storage type");
+    if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth (rows per wavefront) must be >= 1");
+    ctx->plan = pl;
+    return FQNM_OK;
+  }
   if (plan->kernel >= K_STREAM && plan->kernel <= K_TBLOCK_B8) pl.kernel = plan->kernel;
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
@@ -685,7 +807,13 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
   std::vector<fqnm_plan> cand;
   const bool i32 = ctx->prob.itype == FQNM_I32;
   const int vecs32[] = {4, 8, 16}, vecs64[] = {2, 4, 8};
+  if (ctx->dim > 1) {
+    for (int v : {2, 4, 8})
+      if (nd_variant_available(ctx->prob.itype, ctx->pol, v))
+        for (int r : {4, 8, 16, 32, 64}) cand.push_back({K_ND_MARCH, v, r, 0});
+  }
   for (int v : (i32 ? vecs32 : vecs64)) {
+    if (ctx->dim > 1) break;
     const int PER = i32 ? 4 : 2;
     if (v >= 2 * PER) cand.push_back({K_STREAM, v, 1, 0});
     for (int d : {4, 8, 16, 32, 64, 96}) {
@@ -737,7 +865,7 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
   if (st) return st;
   bestp.eval = ctx->plan.eval;
   ctx->plan = bestp;
-  store_plan(plan_key(ctx->prob, ctx->pol), bestp);
+  store_plan(ctx->dim > 1 ? nd_plan_key(ctx) : plan_key(ctx->prob, ctx->pol), bestp);
   return FQNM_OK;
 }
 

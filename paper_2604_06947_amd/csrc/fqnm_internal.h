@@ -18,7 +18,8 @@ enum : int {
   K_TBLOCK_IL = 2,
   K_TBLOCK_B2 = 3,  // workgroup tiles of 2, 4 or 8 wavefronts
   K_TBLOCK_B4 = 4,
-  K_TBLOCK_B8 = 5
+  K_TBLOCK_B8 = 5,
+  K_ND_MARCH = 6  // d-D grids: strips along axis 0 marching along the last axis
 };
 
 // Per-block partial results of the reduction kernel (one record per block).
@@ -46,6 +47,27 @@ bool classical_variant_available(int pol, int kernel, int vec);
 hipError_t launch_classical(int pol, int kernel, int vec, const double* src, double* dst,
                             int64_t n, int bc, int ksteps, int khalo, const XParams& P,
                             hipStream_t s);
+
+// d-dimensional grid (d = 2 or 3), axis 0 contiguous.  Each axis carries its
+// own one-dimensional rule; all axes share the flux kind, storage type and delta.
+struct NdAxis {
+  XParams x;       // the axis's map constants (c, h, a, alpha, delta, lambda)
+  double cp, cm;   // UPWIND: max(c, 0) and min(c, 0)
+  int64_t n;       // cells along the axis
+  int32_t bc;
+  int32_t pad_;
+};
+struct NdParams {
+  NdAxis ax[3];
+  int32_t dim;
+  int32_t pad_;
+};
+bool nd_variant_available(int itype, int pol, int vec);
+// One step of eq:nd_transfer_rule from src to dst; `rows` cells of the last
+// axis per wavefront.  pol is the direct policy (P_UPWIND_POS stands for
+// UPWIND of either sign).
+hipError_t launch_nd(int itype, int pol, int vec, int rows, const void* src, void* dst,
+                     const NdParams& P, long long* d_ledger, hipStream_t s);
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
                             int64_t count, hipStream_t s);

@@ -34,6 +34,8 @@ struct fqnm_ctx {
   bool stream_sync_on_free = false;
   void* d_ws = nullptr;  // diagnostics workspace, grown on demand, freed with the context
   size_t ws_bytes = 0;
+  int dim = 1;           // > 1: d-dimensional grid, prob.n = total cells, axes in nd
+  fqnm::NdParams nd{};
 
   size_t state_bytes() const { return static_cast<size_t>(comp) * prob.n * esize; }
 };

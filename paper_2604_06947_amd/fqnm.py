@@ -32,6 +32,7 @@ I32, I64 = 0, 1
 EVAL_AUTO, EVAL_DIRECT, EVAL_LUT = 0, 1, 2
 KERNEL_STREAM, KERNEL_TBLOCK, KERNEL_TBLOCK_IL = 0, 1, 2
 KERNEL_TBLOCK_B2, KERNEL_TBLOCK_B4, KERNEL_TBLOCK_B8 = 3, 4, 5
+KERNEL_ND_MARCH = 6
 
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",
@@ -41,7 +42,7 @@ EXPORTED = [
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
     "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
     "fqnm_server_drain", "fqnm_server_stats_get", "fqnm_server_now", "fqnm_server_destroy",
-    "fqnm_level_histogram", "fqnm_entropy", "fqnm_step_transitions",
+    "fqnm_level_histogram", "fqnm_entropy", "fqnm_step_transitions", "fqnm_create_nd",
 ]
 
 
@@ -104,6 +105,7 @@ def lib():
             "fqnm_create_from_field": ([P, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_create_on_device": ([P, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_create_classical": ([P, vp, vp, C.POINTER(vp)], C.c_int),
+            "fqnm_create_nd": ([P, i32, vp, vp, C.POINTER(vp)], C.c_int),
             "fqnm_step": ([vp, i64], C.c_int),
             "fqnm_get_state": ([vp, vp], C.c_int),
             "fqnm_state_device": ([vp, C.POINTER(vp)], C.c_int),
@@ -195,6 +197,20 @@ def fqnm_create_classical(prob, u0, stream=None):
         raise ValueError("u0 has the wrong size")
     h = C.c_void_p()
     _check(lib().fqnm_create_classical(C.byref(prob), u0.ctypes.data, stream, C.byref(h)))
+    return h
+
+
+def fqnm_create_nd(axes, q0, stream=None):
+    """d-D grid (Thm dimension_extension).  q0 is C-ordered with the LAST numpy
+    axis contiguous; axes[m] (one fqnm_problem per direction, n = extent) is
+    the direction of numpy axis q0.ndim - 1 - m."""
+    dim = len(axes)
+    q0 = np.ascontiguousarray(q0, dtype=_np_itype(axes[0]))
+    if q0.ndim != dim or tuple(q0.shape[::-1]) != tuple(a.n for a in axes):
+        raise ValueError("q0 shape does not match the axes")
+    arr = (fqnm_problem * dim)(*axes)
+    h = C.c_void_p()
+    _check(lib().fqnm_create_nd(arr, dim, q0.ctypes.data, stream, C.byref(h)))
     return h
 
 

@@ -22,3 +22,6 @@ TRAFFIC_BYTES_PER_LAUNCH = {
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery
 TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
+
+# W6 (2-D Burgers, 4096 x 4096 int32): marching kernel, cells per lane, rows per wavefront
+ND_PLAN_W6 = (8, 12)

@@ -20,6 +20,11 @@ Workloads (all analytic initial data; the paper uses no dataset):
       log-uniform in [256, 65536], step counts uniform in [500, 5000], int32.
   W5  Sod-type Riemann problems for the Euler equations (gamma=1.4), states
       jittered +-20 % around Sod, sizes log-uniform in [2^10, 2^18], t=0.2.
+  W6  2-D inviscid Burgers u_t + (u^2/2)_x + (u^2/2)_y = 0 (directional
+      composition), periodic 4096 x 4096 (2^24 cells), u0 = 0.5 +
+      sin(2 pi x) cos(2 pi y) plus a seeded step h*1[x >= xs], delta=1e-5,
+      Engquist-Osher maps evaluated directly, dt/dx = dt/dy, summed CFL 0.45,
+      1000 steps, int32.
 """
 from __future__ import annotations
 
@@ -108,6 +113,37 @@ def w3_nyquist_advection(r=1e-3, n=1 << 24, steps=2000, seed=3):
     u0 = np.cos((0.9 * np.pi) * i) + 0.01 * z
     return Scalar(UPWIND, r / n, 0.9, u0, steps, PERIODIC, 64, a=1.0,
                   name=f"advection-nyquist N={n} int64 delta/dx={r} dt/dx=0.9 steps={steps}")
+
+
+@dataclass
+class Grid2D:
+    """A 2-D scalar problem: field u0 of shape (ny, nx), x along the last axis."""
+    kind: int
+    delta: float
+    lam: tuple  # (dt/dx, dt/dy)
+    u0: np.ndarray
+    steps: int
+    bc: tuple = (PERIODIC, PERIODIC)
+    width: int = 32
+    a: tuple = (1.0, 1.0)
+    alpha: tuple = (0.0, 0.0)
+    name: str = ""
+
+    @property
+    def shape(self):
+        return self.u0.shape
+
+
+def w6_burgers_2d(nx=4096, ny=4096, steps=1000, seed=6, cfl=0.45, delta=1e-5):
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.2, 1.0)
+    xs = rng.uniform(0.0, 1.0)
+    x = grid(nx)[None, :]
+    y = grid(ny)[:, None]
+    u0 = 0.5 + np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + h * (x >= xs)
+    lam = cfl / (2.0 * float(np.max(np.abs(u0))))  # the two directions share the CFL budget
+    return Grid2D(BURGERS_EO, delta, (lam, lam), u0, steps,
+                  name=f"burgers2d-eo {ny}x{nx} int32 delta={delta} cfl={cfl} steps={steps}")
 
 
 def sine_step_field(x, b, A, m, theta, h, xs):

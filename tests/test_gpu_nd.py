@@ -1,0 +1,211 @@
+"""GPU parity of d-dimensional directional composition (Thm dimension_extension)
+against the oracle's d-D stepper: integer states bit for bit, outflow ledgers
+exactly.  Grids span several strips of the marching kernel along axis 0 with a
+ragged tail, several row blocks along the marching axis with a ragged tail,
+rows whose byte length is not a multiple of 16 (element loads), strips wider
+than the grid, and single rows or columns."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_06947_amd import fqnm as F
+from paper_2604_06947_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KIND = {F.FLUX_UPWIND: O.UPWIND, F.FLUX_BURGERS_EO: O.BURGERS_EO,
+        F.FLUX_BURGERS_GODUNOV: O.BURGERS_GODUNOV, F.FLUX_BURGERS_MURMAN_ROE: O.BURGERS_MURMAN_ROE,
+        F.FLUX_LF_LINEAR: O.LF_LINEAR, F.FLUX_LF_BURGERS: O.LF_BURGERS}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    F.lib()
+
+
+def axes_for(flux, shape, itype, bcs, lams, a_s=None, alphas=None, delta=1e-3):
+    """fqnm_problem per direction; shape is the numpy shape (last axis contiguous)."""
+    dim = len(shape)
+    a_s = a_s or [1.0] * dim
+    alphas = alphas or [0.0] * dim
+    ext = shape[::-1]
+    return [F.make_problem(flux, delta, lams[m], ext[m], bc=bcs[m], itype=itype, a=a_s[m],
+                           alpha=alphas[m]) for m in range(dim)]
+
+
+def oracle_axes(axes):
+    return [O.Problem(KIND[p.flux], p.delta, p.lambda_, bc=p.bc,
+                      width=32 if p.itype == F.I32 else 64, a=p.a, alpha=p.alpha) for p in axes]
+
+
+def gpu_nd(axes, q0, steps, plan=None):
+    h = F.fqnm_create_nd(axes, q0)
+    try:
+        if plan is not None:
+            F.fqnm_set_plan(h, F.KERNEL_ND_MARCH, plan[0], plan[1])
+        F.fqnm_step(h, steps)
+        flat = F.fqnm_get_state(h, F.make_problem(axes[0].flux, axes[0].delta, axes[0].lambda_,
+                                                  int(np.prod(q0.shape)), itype=axes[0].itype))
+        inv = F.fqnm_invariants_get(h)
+    finally:
+        F.fqnm_destroy(h)
+    return flat.astype(np.int64).reshape(q0.shape), inv
+
+
+def field_q(shape, delta, seed, amp=1.0):
+    rng = np.random.default_rng(seed)
+    nd = len(shape)
+    grids = np.meshgrid(*[np.arange(s) / s for s in shape], indexing="ij")
+    u = 0.4 + amp * np.sin(2 * np.pi * grids[-1]) * np.cos(2 * np.pi * grids[0])
+    if nd == 3:
+        u = u + 0.3 * np.sin(2 * np.pi * grids[1])
+    u = u + 0.5 * (grids[-1] >= rng.uniform(0.2, 0.8))
+    return O.quantise(u.ravel(), delta).reshape(shape), float(np.max(np.abs(u)))
+
+
+FLUXES = [(F.FLUX_UPWIND, [1.0, -0.7]), (F.FLUX_BURGERS_EO, None), (F.FLUX_BURGERS_GODUNOV, None),
+          (F.FLUX_BURGERS_MURMAN_ROE, None), (F.FLUX_LF_LINEAR, [0.6, -0.4]),
+          (F.FLUX_LF_BURGERS, None)]
+
+
+def lams_for(flux, umax, a_s, dim):
+    if flux == F.FLUX_UPWIND:
+        return [0.9 / (dim * abs(a)) for a in a_s], None
+    if flux == F.FLUX_LF_LINEAR:
+        al = [1.2 * abs(a) for a in a_s]
+        return [0.9 / (dim * x) for x in al], al
+    if flux == F.FLUX_LF_BURGERS:
+        al = [1.2 * umax] * dim
+        return [0.9 / (dim * x) for x in al], al
+    return [0.9 / (dim * umax)] * dim, None
+
+
+@pytest.mark.parametrize("flux,a_s", FLUXES)
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+@pytest.mark.parametrize("bcs", [(F.BC_PERIODIC, F.BC_PERIODIC), (F.BC_OUTFLOW, F.BC_OUTFLOW),
+                                 (F.BC_OUTFLOW, F.BC_PERIODIC)])
+def test_nd_2d_matches_oracle(flux, a_s, itype, bcs):
+    shape = (45, 602)  # (ny, nx): 2 strips + a tail at V=4 int32; rows 8-byte but not 16-byte aligned
+    q0, umax = field_q(shape, 1e-3, seed=flux)
+    a_s = a_s or [1.0, 1.0]
+    lams, alphas = lams_for(flux, umax, a_s, 2)
+    axes = axes_for(flux, shape, itype, bcs, lams, a_s, alphas)
+    steps = 25
+    ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
+    plans = [(4, 16), (8, 7), (2, 9)] if itype == F.I32 else [(2, 16), (4, 5)]
+    for plan in plans:
+        got, inv = gpu_nd(axes, q0, steps, plan)
+        assert np.array_equal(got, ref), plan
+        assert inv["ledger"][0] == led, plan
+        assert inv["sum"][0] == int(q0.sum()) + led
+
+
+@pytest.mark.parametrize("flux,a_s", [(F.FLUX_UPWIND, [0.5, -1.0, 0.8]),
+                                      (F.FLUX_BURGERS_EO, None), (F.FLUX_BURGERS_GODUNOV, None),
+                                      (F.FLUX_LF_BURGERS, None)])
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+def test_nd_3d_matches_oracle(flux, a_s, itype):
+    shape = (9, 6, 270)  # (nz, ny, nx)
+    q0, umax = field_q(shape, 1e-3, seed=30 + flux)
+    a_s = a_s or [1.0, 1.0, 1.0]
+    lams, alphas = lams_for(flux, umax, a_s, 3)
+    bcs = (F.BC_PERIODIC, F.BC_OUTFLOW, F.BC_OUTFLOW)
+    axes = axes_for(flux, shape, itype, bcs, lams, a_s, alphas)
+    steps = 12
+    ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
+    plans = [(4, 4), (8, 16)] if itype == F.I32 else [(2, 3), (4, 16)]
+    for plan in plans:
+        got, inv = gpu_nd(axes, q0, steps, plan)
+        assert np.array_equal(got, ref), plan
+        assert inv["ledger"][0] == led, plan
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (37, 1), (3, 5), (17, 301), (130, 9),
+                                   (2, 3, 4), (1, 1, 77), (5, 1, 1)])
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+def test_nd_small_and_ragged(shape, bc):
+    q0, umax = field_q(shape, 1e-3, seed=len(shape) * 100 + shape[-1])
+    dim = len(shape)
+    axes = axes_for(F.FLUX_BURGERS_EO, shape, F.I32, [bc] * dim, [0.9 / (dim * umax)] * dim)
+    ref, led = O.step_nd(oracle_axes(axes), q0, 9, return_ledger=True)
+    for plan in [(4, 1), (8, 3), (2, 2)]:
+        got, inv = gpu_nd(axes, q0, 9, plan)
+        assert np.array_equal(got, ref), plan
+        assert inv["ledger"][0] == led
+
+
+def test_nd_counterexample_on_device():
+    # the hand-worked loss of the maximum principle (two rounding steps adding up)
+    q0 = np.zeros((4, 4), dtype=np.int64)
+    q0[1, 1] = 3
+    axes = axes_for(F.FLUX_UPWIND, q0.shape, F.I32, [F.BC_PERIODIC] * 2, [0.5, 0.5])
+    got, _ = gpu_nd(axes, q0, 1)
+    assert got[1, 1] == -1 and got.sum() == 3
+
+
+def test_nd_refusals():
+    q0 = np.zeros((8, 8), dtype=np.int32)
+    ax = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, [F.BC_PERIODIC] * 2, [0.5, 0.5])
+    ax[0].eval = F.EVAL_LUT
+    with pytest.raises(F.FqnmError) as e:
+        F.fqnm_create_nd(ax, q0)
+    assert e.value.status == F.ERR_UNSUPPORTED
+    # each direction within CFL 1, the sum above it
+    q0 = np.full((8, 8), 1000, dtype=np.int32)  # u = 1 at delta 1e-3
+    ax = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, [F.BC_PERIODIC] * 2, [0.6, 0.6])
+    with pytest.raises(F.FqnmError) as e:
+        F.fqnm_create_nd(ax, q0)
+    assert e.value.status == F.ERR_CFL
+    ax = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, [F.BC_PERIODIC] * 2, [0.3, 0.3])
+    ax[1].delta = 2e-3
+    with pytest.raises(F.FqnmError) as e:
+        F.fqnm_create_nd(ax, q0)
+    assert e.value.status == F.ERR_ARG
+
+
+def test_nd_levels_and_autotune():
+    shape = (33, 520)
+    q0, umax = field_q(shape, 1e-3, seed=77)
+    axes = axes_for(F.FLUX_BURGERS_GODUNOV, shape, F.I32, [F.BC_PERIODIC] * 2,
+                    [0.4 / umax, 0.4 / umax])
+    oax = oracle_axes(axes)
+    h = F.fqnm_create_nd(axes, q0)
+    try:
+        F.fqnm_autotune(h, 8)
+        F.fqnm_step(h, 10)
+        ref = O.step_nd(oax, q0, 10)
+        S, _ = F.fqnm_entropy(h)
+        assert S == O.entropy(ref.ravel())
+        f, t, c, rho = F.fqnm_step_transitions(h, ref.size)
+        ref1 = O.step_nd(oax, ref, 1)
+        f0, t0, c0 = O.level_transitions(ref.ravel(), ref1.ravel())
+        assert np.array_equal(f, f0) and np.array_equal(t, t0) and np.array_equal(c, c0)
+        assert rho == O.row_defect(ref.ravel(), ref1.ravel())
+    finally:
+        F.fqnm_destroy(h)
+
+
+def test_nd_w6_full_size_sampled():
+    """W6 at its full 4096 x 4096 cells, 40 steps on the device; cells sampled
+    and checked against the oracle run on the (2s+1)^2 window around each (the
+    5-point composition reaches s cells per direction in s steps)."""
+    w = W.w6_burgers_2d()
+    ny, nx = w.shape
+    q0 = O.quantise(w.u0.ravel(), w.delta, 32).reshape(w.shape)
+    axes = axes_for(F.FLUX_BURGERS_EO, w.shape, F.I32, [F.BC_PERIODIC] * 2, list(w.lam),
+                    delta=w.delta)
+    s = 40
+    got, inv = gpu_nd(axes, q0, s)
+    assert inv["sum"][0] == int(q0.sum())
+    oax = [O.Problem(O.BURGERS_EO, w.delta, w.lam[m], bc=O.OUTFLOW, width=32) for m in range(2)]
+    rng = np.random.default_rng(66)
+    pts = [(0, 0), (ny - 1, nx - 1), (ny // 2, int(w.u0[0].argmax()))]
+    pts += [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, 5), rng.integers(0, nx, 5))]
+    for (j, i) in pts:
+        jj = np.arange(j - s, j + s + 1) % ny
+        ii = np.arange(i - s, i + s + 1) % nx
+        win = q0[np.ix_(jj, ii)]
+        ref = O.step_nd(oax, win, s)
+        assert got[j, i] == ref[s, s], (j, i)
