@@ -99,6 +99,9 @@ def lib():
         L.ofq_entropy.restype = C.c_double
         L.ofq_level_transitions.argtypes = [i64p, i64p, C.c_int64, i64p, i64p, i64p]
         L.ofq_level_transitions.restype = C.c_int64
+        L.ofq_step_euler_density.argtypes = [P, C.c_int64, i64p, f64p, f64p, C.c_int64,
+                                             C.POINTER(C.c_int64)]
+        L.ofq_step_euler_density.restype = C.c_int
         L.ofq_step_nd.argtypes = [C.POINTER(_Problem), C.c_int32, i64p, i64p, C.c_int64,
                                   C.POINTER(C.c_int64)]
         L.ofq_step_nd.restype = C.c_int
@@ -222,6 +225,18 @@ def step_euler(prob: Problem, q3, nsteps, return_ledger=False):
     _check(lib().ofq_step_euler(C.byref(prob.c()), r.size, r, m, E, int(nsteps), led))
     out = np.stack([r, m, E])
     return (out, led) if return_ledger else out
+
+
+def step_euler_density(prob: Problem, qr, m, E, nsteps, return_ledger=False):
+    """Density-only quantised Roe update (Sec. 3.3): integer density counts qr,
+    real momentum m and energy E.  Returns (qr, m, E) [, density ledger]."""
+    qr = np.array(qr, dtype=np.int64, copy=True)
+    m = np.array(m, dtype=np.float64, copy=True)
+    E = np.array(E, dtype=np.float64, copy=True)
+    led = C.c_int64(0)
+    _check(lib().ofq_step_euler_density(C.byref(prob.c()), qr.size, qr, m, E, int(nsteps),
+                                        C.byref(led)))
+    return (qr, m, E, led.value) if return_ledger else (qr, m, E)
 
 
 def euler_flux(prob: Problem, qL, qR):

@@ -717,6 +717,81 @@ int ofq_classical_step_euler(const ofq_problem* p, int64_t n, double* r, double*
   return OFQ_OK;
 }
 
+/* Density-only quantisation of the Roe update (Sec. 3.3, the prototype the
+ * paper runs): the density is an integer count, rho = delta*qr, and moves by
+ * the rounded transfer T = rint((F_rho*lambda)/delta); momentum and energy
+ * stay real-valued and take the classical update U <- U - lambda*(F_R - F_L).
+ * All three fluxes come from the same FP64 Roe flux of the coupled state
+ * (rho, m, E), with the operation order of the other Euler functions.  The
+ * ledger (may be NULL) collects the density counts through outflow ends. */
+int ofq_step_euler_density(const ofq_problem* p, int64_t n, int64_t* qr, double* m, double* E,
+                           int64_t nsteps, int64_t* ledger) {
+  int st = check_problem(p);
+  if (st) return st;
+  if (!euler_kind(p->kind) || n < 1 || nsteps < 0) return OFQ_E_ARG;
+  const double g1 = p->gamma - 1.0;
+  const int fix = p->kind == OFQ_EULER_ROE_EF;
+  ofq_cell* cell = (ofq_cell*)malloc(sizeof(ofq_cell) * (size_t)n);
+  double* F = (double*)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+  int64_t* T = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!cell || !F || !T) { free(cell); free(F); free(T); return OFQ_E_ARG; }
+  for (int64_t s = 0; s < nsteps && st == OFQ_OK; ++s) {
+    for (int64_t i = 0; i < n; ++i) {
+      ofq_cell* o = &cell[i];
+      const double rr = p->delta * (double)qr[i];
+      const double mm = m[i], EE = E[i];
+      double u = mm / rr;
+      double t = 0.5 * mm;
+      t = t * u;
+      t = EE - t;
+      double pp = g1 * t;
+      double H = EE + pp;
+      H = H / rr;
+      o->r = rr; o->m = mm; o->E = EE; o->u = u; o->p = pp; o->H = H; o->s = sqrt(rr);
+      o->c = 0.0;
+      if (fix) {
+        double c = g1 + 1.0;
+        c = c * pp;
+        c = c / rr;
+        o->c = sqrt(c);
+      }
+      o->f0 = mm;
+      double f1 = mm * u;
+      o->f1 = f1 + pp;
+      double f2 = EE + pp;
+      o->f2 = u * f2;
+    }
+    for (int64_t j = 1; j < n; ++j) roe_interface(g1, fix, &cell[j - 1], &cell[j], &F[3 * j], NULL);
+    if (p->bc == OFQ_BC_PERIODIC) {
+      roe_interface(g1, fix, &cell[n - 1], &cell[0], &F[0], NULL);
+      for (int c = 0; c < 3; ++c) F[3 * n + c] = F[c];
+    } else {
+      roe_interface(g1, fix, &cell[0], &cell[0], &F[0], NULL);
+      roe_interface(g1, fix, &cell[n - 1], &cell[n - 1], &F[3 * n], NULL);
+    }
+    for (int64_t j = 0; j <= n; ++j) {
+      double v = F[3 * j] * p->lambda;
+      v = v / p->delta;
+      if ((st = round_to_int(v, &T[j]))) break;
+      if (!fits(p, T[j])) { st = OFQ_E_RANGE; break; }
+    }
+    if (st) break;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t d = T[i + 1] - T[i];
+      const int64_t v = qr[i] - d;
+      if (!fits(p, d) || !fits(p, v)) { st = OFQ_E_RANGE; break; }
+      qr[i] = v;
+      m[i] = m[i] - p->lambda * (F[3 * (i + 1) + 1] - F[3 * i + 1]);
+      E[i] = E[i] - p->lambda * (F[3 * (i + 1) + 2] - F[3 * i + 2]);
+    }
+    if (!st && ledger) *ledger += T[0] - T[n];
+  }
+  free(cell);
+  free(F);
+  free(T);
+  return st;
+}
+
 /* ---------------------------------------------------------------------------
  * Level statistics (Supplementary Information): occupancy c_k, Shannon entropy
  * S = -sum p_k log p_k, and the one-step level-transition counts N_{k'k}.

@@ -639,3 +639,86 @@ def test_euler_mirror_symmetry(kind):
     assert np.abs(a[0] - b[0][::-1]).max() <= 2
     assert np.abs(a[1] + b[1][::-1]).max() <= 2
     assert np.abs(a[2] - b[2][::-1]).max() <= 2
+
+
+# ---------------------------------------------------------------------------
+# Density-only quantisation of the Roe update (Sec. 3.3, the prototype the
+# paper runs): integer density, real momentum and energy.
+# ---------------------------------------------------------------------------
+def _sod_density_state(r):
+    return O.quantise(r.U0[0], r.delta), r.U0[1].copy(), r.U0[2].copy()
+
+
+@pytest.mark.parametrize("kind", [O.EULER_ROE, O.EULER_ROE_EF])
+def test_density_only_one_step_against_fp64_roe(kind):
+    # From the same state the fluxes are the FP64 scheme's own, so after one
+    # step m and E equal the classical update bit for bit, and the density
+    # differs from it only by the two roundings of its transfers: at most delta
+    # (each transfer within delta/2 of lambda*F_rho).
+    rng = np.random.default_rng(41)
+    n = 300
+    r = W.sod_request(n, kind=kind)
+    p = O.Problem(kind, r.delta, r.lam, bc=O.OUTFLOW, gamma=r.gamma)
+    qr = O.quantise(r.U0[0] * (1 + 0.1 * rng.random(n)), r.delta)
+    m = r.U0[1] + 0.05 * rng.standard_normal(n)  # keeps the pressure positive
+    E = r.U0[2] * (1 + 0.1 * rng.random(n))
+    q1, m1, E1 = O.step_euler_density(p, qr, m, E, 1)
+    U = np.stack([O.reconstruct(qr, r.delta), m, E])
+    fp = O.classical_step_euler(p, U, 1)
+    assert np.array_equal(m1.view(np.uint64), fp[1].view(np.uint64))
+    assert np.array_equal(E1.view(np.uint64), fp[2].view(np.uint64))
+    assert np.abs(O.reconstruct(q1, r.delta) - fp[0]).max() <= r.delta * (1 + 1e-9)
+
+
+def test_density_only_conservation_and_fixed_point():
+    r = W.sod_request(400)
+    p = O.Problem(O.EULER_ROE_EF, r.delta, r.lam, bc=O.OUTFLOW, gamma=r.gamma)
+    qr, m, E = _sod_density_state(r)
+    cur, led_total = qr, 0
+    mm, EE = m, E
+    for _ in range(30):
+        nxt, mm, EE, led = O.step_euler_density(p, cur, mm, EE, 1, return_ledger=True)
+        assert int(nxt.sum()) - int(cur.sum()) == led
+        led_total += led
+        cur = nxt
+    pp = O.Problem(O.EULER_ROE_EF, r.delta, r.lam, bc=O.PERIODIC, gamma=r.gamma)
+    a, _, _ = O.step_euler_density(pp, qr, m, E, 50)
+    assert int(a.sum()) == int(qr.sum())
+    const = O.step_euler_density(p, np.full(20, 700000), np.full(20, 0.2), np.full(20, 2.5), 40)
+    assert np.all(const[0] == 700000) and np.all(const[1] == 0.2) and np.all(const[2] == 2.5)
+
+
+@pytest.mark.parametrize("kind", [O.EULER_ROE_EF, O.EULER_ROE])
+def test_density_only_sod_against_exact(kind):
+    # the paper's experiment: Sod at t = 0.2 against the exact Riemann solution
+    n = 1024
+    r = W.sod_request(n, kind=kind)
+    p = O.Problem(kind, r.delta, r.lam, bc=O.OUTFLOW, gamma=r.gamma)
+    qr, m, E = _sod_density_state(r)
+    q, m1, E1 = O.step_euler_density(p, qr, m, E, r.steps)
+    rho = O.reconstruct(q, r.delta)
+    x = W.grid(n)
+    xd = (n // 2 - 0.5) / n
+    ref, _, _ = X.riemann_exact(r.left, r.right, (x - xd) / r.t_final)
+    err = float(np.mean(np.abs(rho - ref)))
+    fp = O.classical_step_euler(p, np.stack([O.reconstruct(qr, r.delta), m, E]), r.steps)
+    err_fp = float(np.mean(np.abs(fp[0] - ref)))
+    assert err <= 0.02 and err <= 2 * err_fp
+    mid = 0.5 * (0.26557 + 0.125)
+    k = np.where((rho[:-1] > mid) & (rho[1:] <= mid))[0]
+    assert abs(x[k[-1]] - 0.8504) < 4.0 / n
+
+
+def test_density_only_mirror_symmetry():
+    n = 512
+
+    def run(left, right):
+        r = W.sod_request(n, left, right, kind=O.EULER_ROE_EF)
+        p = O.Problem(O.EULER_ROE_EF, r.delta, r.lam, bc=O.OUTFLOW, gamma=1.4)
+        return O.step_euler_density(p, *_sod_density_state(r), r.steps)
+
+    a = run((1.0, 0.75, 1.0), (0.125, 0.0, 0.1))
+    b = run((0.125, 0.0, 0.1), (1.0, -0.75, 1.0))
+    assert np.abs(a[0] - b[0][::-1]).max() <= 2
+    assert np.abs(a[1] + b[1][::-1]).max() <= 1e-9
+    assert np.abs(a[2] - b[2][::-1]).max() <= 1e-9
