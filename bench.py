@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels, nd")
+    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels, nd, euler")
     return ap.parse_args()
 
 
@@ -305,6 +305,38 @@ def bench_nd(F, W, plans, stream, reps=3):
         "conservation_ok": inv["sum"][0] == int(q0.astype(np.int64).sum())}}
 
 
+def bench_euler(F, W, stream, n=1 << 20, steps=200, reps=3):
+    """Sod at 2^20 cells, 200 steps of the single-grid Euler kernel: the
+    componentwise quantisation (all of rho, m, E counted) and the density-only
+    prototype (FP64 m and E).  Device time of the steps by HIP events."""
+    import torch
+    out = {}
+    for tag, kind in (("componentwise", F.FLUX_EULER_ROE_EF),
+                      ("density_only", F.FLUX_EULER_ROE_EF_DENSITY)):
+        r = W.sod_request(n, kind=6)
+        prob = F.make_problem(kind, r.delta, r.lam, n, bc=F.BC_OUTFLOW, itype=F.I64, gamma=1.4)
+        ts = []
+        for _ in range(reps + 1):
+            h = F.fqnm_create_from_field(prob, r.U0.ravel(), stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            F.fqnm_step(h, steps)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+            F.fqnm_destroy(h)
+        t = float(np.median(ts[1:]))
+        rate = n * steps / t
+        ach = 48.0 * n / (t / steps) / 1e9
+        log(f"[bench] Sod {tag} {rate:.3e} cell-updates/s")
+        out[f"sod_2e20_{tag}"] = {"cell_updates_per_s": rate, "ms_per_step": t / steps * 1e3,
+                                  "kernel_GBps_algorithmic": ach,
+                                  "frac_of_hbm": ach / HBM_PEAK_GBS,
+                                  "bound": "fp64 alu (divisions, square roots)"}
+    return out
+
+
 def bench_levels(F, W, stream, reps=5):
     """Level statistics at the headline size (2^20 int32 cells, Burgers EO after
     2000 steps): histogram + entropy, and one transition step with its counts
@@ -389,6 +421,8 @@ def run_extras_only(args, F, W, plans, stream):
         extras.update(bench_levels(F, W, stream))
     elif args.only == "nd":
         extras.update(bench_nd(F, W, plans, stream))
+    elif args.only == "euler":
+        extras.update(bench_euler(F, W, stream))
     print(json.dumps({"extras": extras}), flush=True)
 
 
@@ -490,6 +524,9 @@ def main():
     # ---------------- 2-D directional composition -------------------------------------
     if not args.no_extras and args.only in ("", "nd"):
         extras.update(bench_nd(F, W, plans, stream))
+    # ---------------- single-grid Sod: componentwise and density-only -----------------
+    if not args.no_extras and args.only in ("", "euler"):
+        extras.update(bench_euler(F, W, stream))
     # ---------------- level statistics (entropy, transitions) -------------------------
     if not args.no_extras and args.only in ("", "levels"):
         extras.update(bench_levels(F, W, stream))

@@ -70,7 +70,13 @@ typedef enum {
   FQNM_FLUX_EULER_ROE = 5,       /* Euler equations, 3 components, Roe flux in FP64 then
                                     T_c = rint((F_c*lambda)/delta) per component (Sec. 3.3)      */
   FQNM_FLUX_EULER_ROE_EF = 6,    /* as above with an entropy fix of the acoustic waves            */
-  FQNM_FLUX_BURGERS_MURMAN_ROE = 7 /* f = u^2/2, two-point Murman-Roe flux, one rounding         */
+  FQNM_FLUX_BURGERS_MURMAN_ROE = 7, /* f = u^2/2, two-point Murman-Roe flux, one rounding        */
+  FQNM_FLUX_EULER_ROE_DENSITY = 8, /* Euler, density-only quantisation (the prototype of Sec. 3.3):
+                                    component 0 holds int64 density counts moved by
+                                    T = rint((F_rho*lambda)/delta); components 1 and 2 hold FP64
+                                    m and E (8-byte slots), updated U - lambda*(F_R - F_L); all
+                                    fluxes from one FP64 Roe flux of (delta*q_rho, m, E)        */
+  FQNM_FLUX_EULER_ROE_EF_DENSITY = 9 /* as above with the entropy fix of FQNM_FLUX_EULER_ROE_EF  */
 } fqnm_flux;
 
 typedef enum { FQNM_BC_PERIODIC = 0, FQNM_BC_OUTFLOW = 1 } fqnm_bc;
@@ -144,7 +150,8 @@ const char* fqnm_last_error(void);
 const char* fqnm_version(void);
 
 /* Create a solver from an integer initial state q0_host (n or 3n integers of
- * the problem's itype).  Validates the problem: positive finite delta, dx,
+ * the problem's itype; for the density-only Euler kinds 3n 8-byte slots: n
+ * int64 density counts, then n FP64 momenta and n FP64 energies).  Validates the problem: positive finite delta, dx,
  * lambda (FQNM_ERR_ARG); the CFL number over [min q0, max q0] for scalar
  * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^52 so that q converts
  * to FP64 exactly, q^2 < 2^53 for Burgers kinds, and for I32 that
@@ -154,7 +161,8 @@ fqnm_status fqnm_create(const fqnm_problem* prob, const void* q0_host, void* hip
                         fqnm_ctx** out);
 
 /* As fqnm_create, from a real initial field u0_host (n or 3n doubles): the
- * device quantises q0_i = rint(u0_i / delta) (Sec. 2, eq:quantisation). */
+ * device quantises q0_i = rint(u0_i / delta) (Sec. 2, eq:quantisation); the
+ * density-only Euler kinds quantise the density and keep m and E as given. */
 fqnm_status fqnm_create_from_field(const fqnm_problem* prob, const double* u0_host,
                                    void* hip_stream, fqnm_ctx** out);
 
@@ -175,13 +183,15 @@ fqnm_status fqnm_get_state(fqnm_ctx* ctx, void* q_host);
 fqnm_status fqnm_state_device(fqnm_ctx* ctx, void** d_q);
 
 /* Reconstruct u_i = delta*q_i (eq:reconstruction_operator) into u_host
- * (components*n doubles).  Syncs. */
+ * (components*n doubles; density-only Euler kinds: delta*q_rho, then m and E
+ * as they are).  Syncs. */
 fqnm_status fqnm_reconstruct(fqnm_ctx* ctx, double* u_host);
 
 /* As fqnm_reconstruct into device memory d_u; asynchronous. */
 fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u);
 
-/* Exact sums, extrema, total variation and boundary ledger.  Syncs. */
+/* Exact sums, extrema, total variation and boundary ledger of the integer
+ * components (density-only Euler kinds: the density alone).  Syncs. */
 fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out);
 
 fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out);

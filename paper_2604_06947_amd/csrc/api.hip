@@ -31,7 +31,12 @@ fqnm_status hip_fail(hipError_t e, const char* what) {
   return fail(FQNM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool is_euler(int flux) { return flux == FQNM_FLUX_EULER_ROE || flux == FQNM_FLUX_EULER_ROE_EF; }
+bool is_euler(int flux) {
+  return flux == FQNM_FLUX_EULER_ROE || flux == FQNM_FLUX_EULER_ROE_EF || is_euler_density(flux);
+}
+bool is_euler_density(int flux) {
+  return flux == FQNM_FLUX_EULER_ROE_DENSITY || flux == FQNM_FLUX_EULER_ROE_EF_DENSITY;
+}
 bool is_burgers(int flux) {
   return flux == FQNM_FLUX_BURGERS_EO || flux == FQNM_FLUX_BURGERS_GODUNOV ||
          flux == FQNM_FLUX_BURGERS_MURMAN_ROE || flux == FQNM_FLUX_LF_BURGERS;
@@ -41,7 +46,7 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 fqnm_status validate_problem(const fqnm_problem* p) {
   if (!p) return fail(FQNM_ERR_ARG, "problem is NULL");
   if (p->abi_version != FQNM_ABI_VERSION) return fail(FQNM_ERR_ARG, "abi_version mismatch");
-  if (p->flux < 0 || p->flux > FQNM_FLUX_BURGERS_MURMAN_ROE)
+  if (p->flux < 0 || p->flux > FQNM_FLUX_EULER_ROE_EF_DENSITY)
     return fail(FQNM_ERR_ARG, "unknown flux kind");
   if (p->bc != FQNM_BC_PERIODIC && p->bc != FQNM_BC_OUTFLOW)
     return fail(FQNM_ERR_ARG, "unknown boundary kind");
@@ -318,7 +323,8 @@ fqnm_status fqnm::ctx_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi) 
 static fqnm_status ctx_finish(fqnm_ctx* ctx) {
   const fqnm_problem& p = ctx->prob;
   if (ctx->euler) {
-    for (int c = 0; c < 3; ++c) {
+    const bool dens = is_euler_density(p.flux);
+    for (int c = 0; c < (dens ? 1 : 3); ++c) {  // density-only: m and E are FP64
       int64_t lo, hi;
       fqnm_status st = ctx_minmax(ctx, c, &lo, &hi);
       if (st) return st;
@@ -329,7 +335,8 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     ctx->eparams.delta = p.delta;
     ctx->eparams.lambda = p.lambda;
     ctx->eparams.g1 = p.gamma - 1.0;
-    ctx->eparams.fix = p.flux == FQNM_FLUX_EULER_ROE_EF;
+    ctx->eparams.fix = p.flux == FQNM_FLUX_EULER_ROE_EF || p.flux == FQNM_FLUX_EULER_ROE_EF_DENSITY;
+    ctx->eparams.dens = dens;
     return FQNM_OK;
   }
   int64_t lo, hi;
@@ -429,9 +436,14 @@ fqnm_status fqnm_create_from_field(const fqnm_problem* prob, const double* u0_ho
     hipError_t e = hipMemcpyAsync(ctx->d_u, u0_host, sizeof(double) * total,
                                   hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream);
+    const bool dens = is_euler_density(prob->flux);
     if (e == hipSuccess)
-      e = launch_quantise(prob->itype, ctx->d_u, ctx->buf[0], total, prob->delta, ctx->d_err,
-                          ctx->stream);
+      e = launch_quantise(prob->itype, ctx->d_u, ctx->buf[0], dens ? prob->n : total, prob->delta,
+                          ctx->d_err, ctx->stream);
+    if (e == hipSuccess && dens)  // momentum and energy stay real-valued
+      e = hipMemcpyAsync(static_cast<char*>(ctx->buf[0]) + sizeof(double) * prob->n,
+                         ctx->d_u + prob->n, sizeof(double) * 2 * prob->n,
+                         hipMemcpyDeviceToDevice, ctx->stream);
     int herr = 0;
     if (e == hipSuccess)
       e = hipMemcpyAsync(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
@@ -654,6 +666,15 @@ fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u) {
                            ctx->stream), "copy field");
     return FQNM_OK;
   }
+  if (ctx->euler && ctx->eparams.dens) {
+    const int64_t n = ctx->prob.n;
+    CTX_HIP(launch_reconstruct(ctx->prob.itype, ctx->buf[ctx->cur], d_u, n, ctx->prob.delta,
+                               ctx->stream), "reconstruct");
+    CTX_HIP(hipMemcpyAsync(d_u + n, static_cast<const char*>(ctx->buf[ctx->cur]) + 8 * n,
+                           sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, ctx->stream),
+            "copy m, E");
+    return FQNM_OK;
+  }
   CTX_HIP(launch_reconstruct(ctx->prob.itype, ctx->buf[ctx->cur], d_u, ctx->comp * ctx->prob.n,
                              ctx->prob.delta, ctx->stream), "reconstruct");
   return FQNM_OK;
@@ -678,14 +699,15 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
   if (ctx->classical) return fail(FQNM_ERR_UNSUPPORTED, "no integer invariants for the FP64 twin");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
   std::memset(out, 0, sizeof *out);
-  out->components = ctx->comp;
+  const int ncomp = ctx->euler && ctx->eparams.dens ? 1 : ctx->comp;  // integer components
+  out->components = ncomp;
   out->steps_done = ctx->steps_done;
   const int64_t n = ctx->prob.n;
   const int64_t nb = reduce_blocks(n);
   if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
     return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
   std::vector<ReducePartial> h(nb);
-  for (int c = 0; c < ctx->comp; ++c) {
+  for (int c = 0; c < ncomp; ++c) {
     const char* q = static_cast<const char*>(ctx->buf[ctx->cur]) + c * n * ctx->esize;
     CTX_HIP(launch_reduce(ctx->prob.itype, q, n, ctx->prob.bc == FQNM_BC_PERIODIC, ctx->d_red,
                           ctx->stream), "reduce");
@@ -712,7 +734,7 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
   CTX_HIP(hipMemcpyAsync(led, ctx->d_ledger, sizeof led, hipMemcpyDeviceToHost, ctx->stream),
           "copy ledger");
   CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
-  for (int c = 0; c < 3; ++c) out->ledger[c] = c < ctx->comp ? led[c] : 0;
+  for (int c = 0; c < 3; ++c) out->ledger[c] = c < ncomp ? led[c] : 0;
   return FQNM_OK;
 }
 

@@ -9,7 +9,13 @@
 // applies the integer telescoping update of eq:update_rule_conservative_form
 // to each component, so sum(q_c) changes only by the boundary counts.
 //
-// Layout: three int64 arrays of n cells (rho, m, E) back to back, ping-pong.
+// The density-only prototype the paper actually runs is the same kernel with
+// EulerParams::dens set: component 0 holds the integer density counts, and
+// components 1 and 2 hold FP64 momentum and energy (their bit patterns in the
+// 8-byte slots).  Only the density flux is rounded, T_rho = rint((F_rho*lambda)/
+// delta); m and E take the classical update U - lambda*(F_R - F_L).
+//
+// Layout: three 8-byte arrays of n cells (rho, m, E) back to back, ping-pong.
 // A 256-thread block loads cells [b0-1, b0+255), computes the per-cell
 // primitives once into LDS, evaluates the 255 interfaces between them, and
 // updates the 254 cells [b0, b0+254).  Cells outside [0, n) are ghost copies
@@ -33,12 +39,10 @@ struct Prim {
   double r, u, p, H, s, c, f0, f1, f2;
 };
 
-__device__ __forceinline__ Prim cell_primitives(const EulerParams& E, int64_t qr, int64_t qm,
-                                                int64_t qE) {
+// Primitives of a cell from its conserved values (r, m, en) in FP64.
+__device__ __forceinline__ Prim cell_primitives_f(const EulerParams& E, double r, double m,
+                                                  double en) {
   Prim o;
-  const double r = E.delta * static_cast<double>(qr);
-  const double m = E.delta * static_cast<double>(qm);
-  const double en = E.delta * static_cast<double>(qE);
   const double u = m / r;
   double t = 0.5 * m;
   t = t * u;
@@ -67,6 +71,18 @@ __device__ __forceinline__ Prim cell_primitives(const EulerParams& E, int64_t qr
   return o;
 }
 
+// Cell of the 8-byte state slots: counts times delta, or (density-only) the
+// density counts with FP64 m and E.
+__device__ __forceinline__ Prim cell_primitives(const EulerParams& E, int64_t qr, int64_t qm,
+                                                int64_t qE) {
+  const double r = E.delta * static_cast<double>(qr);
+  if (E.dens)
+    return cell_primitives_f(E, r, __builtin_bit_cast(double, qm), __builtin_bit_cast(double, qE));
+  const double m = E.delta * static_cast<double>(qm);
+  const double en = E.delta * static_cast<double>(qE);
+  return cell_primitives_f(E, r, m, en);
+}
+
 __device__ __forceinline__ double acoustic_fix(double l, double e, double lLk, double lRk) {
   const double d1 = l - lLk;
   const double d2 = lRk - l;
@@ -83,7 +99,8 @@ __device__ __forceinline__ double acoustic_fix(double l, double e, double lLk, d
   return e;
 }
 
-// Roe flux of two cells, then the three quantised transfers.
+// Roe flux of two cells, then the three quantised transfers (density-only:
+// the density transfer and the FP64 fluxes of m and E as bit patterns).
 __device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L, const Prim& R,
                                              int64_t T[3]) {
   const double w = L.s + R.s;
@@ -151,9 +168,13 @@ __device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L
     F = 0.5 * F;
     const double h = 0.5 * D[c];
     F = F - h;
-    double v = F * E.lambda;
-    v = v / E.delta;
-    T[c] = static_cast<int64_t>(rint(v));
+    if (E.dens && c > 0) {
+      T[c] = __builtin_bit_cast(int64_t, F);
+    } else {
+      double v = F * E.lambda;
+      v = v / E.delta;
+      T[c] = static_cast<int64_t>(rint(v));
+    }
   }
 }
 
@@ -183,18 +204,27 @@ __device__ __forceinline__ void euler_tile_step(const int64_t* __restrict__ src,
   __syncthreads();
   if (t >= 1 && t <= ECELLS && g < n) {
     dst[g] = qr - (T[0] - s_T[0][t - 1]);
-    dst[n + g] = qm - (T[1] - s_T[1][t - 1]);
-    dst[2 * n + g] = qE - (T[2] - s_T[2][t - 1]);
+    if (E.dens) {
+      // classical update of the real-valued components
+      const double dm = __builtin_bit_cast(double, T[1]) - __builtin_bit_cast(double, s_T[1][t - 1]);
+      const double dE = __builtin_bit_cast(double, T[2]) - __builtin_bit_cast(double, s_T[2][t - 1]);
+      const double tm = E.lambda * dm;
+      const double tE = E.lambda * dE;
+      dst[n + g] = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qm) - tm);
+      dst[2 * n + g] = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qE) - tE);
+    } else {
+      dst[n + g] = qm - (T[1] - s_T[1][t - 1]);
+      dst[2 * n + g] = qE - (T[2] - s_T[2][t - 1]);
+    }
+    const int nled = E.dens ? 1 : 3;  // density-only: only the counts have a ledger
     if (bc == FQNM_BC_OUTFLOW) {
       if (g == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < nled; ++c)
           atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
                     static_cast<unsigned long long>(s_T[c][t - 1]));
       }
       if (g == n - 1) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < nled; ++c)
           atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
                     static_cast<unsigned long long>(-static_cast<long long>(T[c])));
       }

@@ -80,12 +80,13 @@ int64_t reduce_blocks(int64_t n);
 hipError_t launch_reduce(int itype, const void* q, int64_t n, int periodic, ReducePartial* out,
                          hipStream_t s);
 
-// Euler (3 x int64, structure of arrays): one step per launch.
+// Euler (3 x 8-byte components, structure of arrays): one step per launch.
 struct EulerParams {
   double delta;
   double lambda;
   double g1;  // gamma - 1
   int fix;    // entropy fix on the acoustic waves
+  int dens;   // density-only: components 1, 2 hold FP64 m and E (bit patterns)
 };
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
                              const EulerParams& E, long long* d_ledger, hipStream_t s);

@@ -47,6 +47,7 @@ fqnm_status hip_fail(hipError_t e, const char* what);
 fqnm_status validate_problem(const fqnm_problem* p);
 fqnm_status validate_range(const fqnm_problem& p, int64_t lo, int64_t hi);
 bool is_euler(int flux);
+bool is_euler_density(int flux);  // Euler with only the density quantised
 bool is_burgers(int flux);
 int policy_of(const fqnm_problem& p, bool lut);
 int direct_split_policy(const fqnm_problem& p);

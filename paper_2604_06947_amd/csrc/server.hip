@@ -278,7 +278,9 @@ bool run_tick(fqnm_server* s) {
       R.E.delta = r->prob.delta;
       R.E.lambda = r->prob.lambda;
       R.E.g1 = r->prob.gamma - 1.0;
-      R.E.fix = r->prob.flux == FQNM_FLUX_EULER_ROE_EF;
+      R.E.fix = r->prob.flux == FQNM_FLUX_EULER_ROE_EF ||
+                r->prob.flux == FQNM_FLUX_EULER_ROE_EF_DENSITY;
+      R.E.dens = is_euler_density(r->prob.flux);
       const int32_t id = static_cast<int32_t>(er.size());
       er.push_back(R);
       const int64_t nt = euler_tiles(r->prob.n);
@@ -475,7 +477,8 @@ fqnm_status fqnm_server_submit(fqnm_server* s, const fqnm_problem* prob, const v
   const size_t sb = r->comp * prob->n * r->es;
   r->q0.assign(static_cast<const char*>(q0_host), static_cast<const char*>(q0_host) + sb);
   // range checks on the host copy, as at create
-  for (int c = 0; c < r->comp && st == FQNM_OK; ++c) {
+  const int ncheck = is_euler_density(prob->flux) ? 1 : r->comp;  // m, E of density-only are FP64
+  for (int c = 0; c < ncheck && st == FQNM_OK; ++c) {
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     for (int64_t i = 0; i < prob->n; ++i) {
       const int64_t v = r->es == 4 ? reinterpret_cast<const int32_t*>(r->q0.data())[i]

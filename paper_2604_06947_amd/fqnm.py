@@ -27,6 +27,8 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_CFL", -3: "ERR_RANGE", -4: "ERR
 # fqnm_flux, fqnm_bc, fqnm_itype, fqnm_eval
 FLUX_UPWIND, FLUX_BURGERS_EO, FLUX_BURGERS_GODUNOV, FLUX_LF_LINEAR, FLUX_LF_BURGERS = 0, 1, 2, 3, 4
 FLUX_EULER_ROE, FLUX_EULER_ROE_EF, FLUX_BURGERS_MURMAN_ROE = 5, 6, 7
+FLUX_EULER_ROE_DENSITY, FLUX_EULER_ROE_EF_DENSITY = 8, 9
+EULER_KINDS = (FLUX_EULER_ROE, FLUX_EULER_ROE_EF, FLUX_EULER_ROE_DENSITY, FLUX_EULER_ROE_EF_DENSITY)
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 I32, I64 = 0, 1
 EVAL_AUTO, EVAL_DIRECT, EVAL_LUT = 0, 1, 2
@@ -161,7 +163,20 @@ def _np_itype(prob):
 
 
 def _components(prob):
-    return 3 if prob.flux in (FLUX_EULER_ROE, FLUX_EULER_ROE_EF) else 1
+    return 3 if prob.flux in EULER_KINDS else 1
+
+
+def density_only_state(raw):
+    """Split the (3, n) int64 state of a density-only Euler context into
+    (density counts, FP64 m, FP64 E)."""
+    raw = np.ascontiguousarray(raw, dtype=np.int64)
+    return raw[0].copy(), raw[1].view(np.float64).copy(), raw[2].view(np.float64).copy()
+
+
+def density_only_raw(qr, m, E):
+    """The 3n 8-byte slots of a density-only Euler state, for fqnm_create."""
+    return np.stack([np.asarray(qr, np.int64), np.asarray(m, np.float64).view(np.int64),
+                     np.asarray(E, np.float64).view(np.int64)])
 
 
 def fqnm_last_error():
