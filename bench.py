@@ -31,12 +31,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_sources_sha():
+def kernel_sources_sha(sources=None):
     import hashlib
     from paper_2604_06947_amd import plans
     pkg = os.path.join(ROOT, "paper_2604_06947_amd")
     h = hashlib.sha256()
-    for rel in plans.KERNEL_SOURCES:
+    for rel in sources or plans.KERNEL_SOURCES:
         with open(os.path.join(pkg, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -301,6 +301,11 @@ def bench_nd(F, W, plans, stream, reps=3):
         "kernel": "k_nd_march<int, P_EO, %d, 2>" % plans.ND_PLAN_W6[0],
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "bytes_per_cell_update": 8,
+                     "traffic": (plans.TRAFFIC_BYTES_PER_LAUNCH["w6"]
+                                 if kernel_sources_sha(plans.ND_KERNEL_SOURCES)
+                                 == plans.ND_MEASURED_SOURCES_SHA
+                                 and tuple(plans.ND_PLAN_W6) == (8, 12) else None),
+                     "algorithmic_bytes_per_launch": 8 * cells,
                      "avg_launch_us": t / w.steps * 1e6},
         "conservation_ok": inv["sum"][0] == int(q0.astype(np.int64).sum())}}
 
