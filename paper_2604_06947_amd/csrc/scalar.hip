@@ -280,6 +280,31 @@ __device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, cons
   }
 }
 
+// One step of a tile whose cells are held as their table addresses in the
+// wavefront's LDS slice: a = base + 8*(q - lo).  The update q - (F - F_left)
+// becomes a + 8*(F_left - F), so a step costs one clamp, one LDS read, one
+// add, one subtraction and one shift-add per cell.  The clamp keeps every
+// read inside the slice; in-domain cells never need it (maximum principle),
+// only discarded halo lanes can drift.  Int32 tables, interior tiles.
+template <int V>
+__device__ __forceinline__ void tb_step_addr(uint32_t (&a)[V], uint32_t end) {
+  uint32_t pp[V], pm[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const uint32_t x = a[j] < end ? a[j] : end;
+    const uint64_t e = *(lds_u64*)(static_cast<uintptr_t>(x));
+    pp[j] = static_cast<uint32_t>(e);
+    pm[j] = static_cast<uint32_t>(e >> 32);
+  }
+  const uint32_t pmn = lane_from_next<uint32_t>(pm[0]);
+  uint32_t F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) F[j] = pp[j] + (j + 1 < V ? pm[j + 1] : pmn);
+  const uint32_t Fl = lane_from_prev<uint32_t>(F[V - 1]);
+#pragma unroll
+  for (int j = 0; j < V; ++j) a[j] += ((j == 0 ? Fl : F[j - 1]) - F[j]) << 3;
+}
+
 template <typename IT, int POL, int V>
 __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* __restrict__ dst,
                                                 int64_t n, int bc, int ksteps, int khalo,
@@ -342,8 +367,16 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
       const LdsWindow Wn{base - (static_cast<uint32_t>(mn) << 3),
                          base + (static_cast<uint32_t>(span) << 3)};
       if (plain) {
-        for (int s = 0; s < ksteps; ++s)
-          tb_step<IT, POL, V, false, true>(P, L, Wn, q, g0, n, false, led);
+        const uint32_t end = base + (static_cast<uint32_t>(span) << 3);
+        uint32_t a[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(mn)) << 3);
+        for (int s = 0; s < ksteps; ++s) tb_step_addr<V>(a, end);
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          q[j] = static_cast<IT>(static_cast<uint32_t>(mn) +
+                                 static_cast<uint32_t>(static_cast<int32_t>(a[j] - base) >> 3));
       } else {
         for (int s = 0; s < ksteps; ++s)
           tb_step<IT, POL, V, true, true>(P, L, Wn, q, g0, n, own_right, led);
