@@ -135,8 +135,11 @@ typedef struct {
  * reads coalesce), split kinds only; 3, 4, 5 = temporal blocking in
  * workgroup tiles of 2, 4 or 8 wavefronts; 6 = the d-D marching kernel (the
  * only one of d-D contexts): a wavefront owns 64*vec cells of axis 0 and
- * marches `depth` cells along the last axis, one step per pass.  Zero fields
- * mean "keep". */
+ * marches `depth` cells along the last axis, one step per pass; 7, 8 =
+ * workgroup tiles of 4 or 8 wavefronts whose windows (64*vec cells, vec 2 or
+ * 4) overlap by 16 cells and are refreshed from their neighbours every 8
+ * steps, `depth` <= 64*vec - 16 steps per pass (int32 tables on periodic
+ * grids only).  Zero fields mean "keep". */
 typedef struct {
   int32_t kernel;
   int32_t vec;          /* cells per lane                                                */

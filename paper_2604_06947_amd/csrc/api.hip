@@ -607,6 +607,11 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
     } else if (ctx->euler) {
       e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
                             p.bc, ctx->eparams, ctx->d_ledger, ctx->stream);
+    } else if (pl.kernel == K_TBLOCK_WG4 || pl.kernel == K_TBLOCK_WG8) {
+      k = std::min<int64_t>(pl.depth, left);
+      e = launch_tblock_wg(pl.kernel == K_TBLOCK_WG4 ? 4 : 8, pl.vec,
+                           static_cast<const int32_t*>(src), static_cast<int32_t*>(dst), p.n,
+                           static_cast<int>(k), ctx->xp, ctx->stream);
     } else if (pl.kernel == K_STREAM) {
       e = launch_scalar(p.itype, ctx->pol, K_STREAM, pl.vec, src, dst, p.n, p.bc, 1, 0, ctx->xp,
                         ctx->d_ledger, ctx->stream);
@@ -792,10 +797,21 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
     ctx->plan = pl;
     return FQNM_OK;
   }
-  if (plan->kernel >= K_STREAM && plan->kernel <= K_TBLOCK_B8) pl.kernel = plan->kernel;
+  if ((plan->kernel >= K_STREAM && plan->kernel <= K_TBLOCK_B8) ||
+      plan->kernel == K_TBLOCK_WG4 || plan->kernel == K_TBLOCK_WG8)
+    pl.kernel = plan->kernel;
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
   if (plan->depth) pl.depth = plan->depth;
+  if (pl.kernel == K_TBLOCK_WG4 || pl.kernel == K_TBLOCK_WG8) {
+    if (ctx->classical || ctx->prob.itype != FQNM_I32 || ctx->pol != P_LUT ||
+        ctx->prob.bc != FQNM_BC_PERIODIC)
+      return fail(FQNM_ERR_ARG, "overlapping-window tiles need int32 tables on a periodic grid");
+    if (!tblock_wg_valid(pl.kernel == K_TBLOCK_WG4 ? 4 : 8, pl.vec, pl.depth))
+      return fail(FQNM_ERR_ARG, "vec must be 2 or 4 and depth at most 64*vec - 16");
+    ctx->plan = pl;
+    return FQNM_OK;
+  }
   if (ctx->classical ? !classical_variant_available(ctx->pol, pl.kernel, pl.vec)
                      : !scalar_variant_available(ctx->prob.itype, ctx->pol, pl.kernel, pl.vec))
     return fail(FQNM_ERR_ARG, "vec not available for this storage type");
@@ -848,6 +864,13 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
         if (scalar_tile_positions(kb, v) - 2 * kh >= scalar_tile_positions(kb, v) / 2)
           cand.push_back({kb, v, d, 0});
       }
+    }
+    if (v == 4 && ctx->prob.itype == FQNM_I32 && ctx->pol == P_LUT &&
+        ctx->prob.bc == FQNM_BC_PERIODIC) {
+      for (int kw : {K_TBLOCK_WG4, K_TBLOCK_WG8})
+        for (int vv : {2, 4})
+          for (int d : {24, 48, 64, 96})
+            if (tblock_wg_valid(kw == K_TBLOCK_WG4 ? 4 : 8, vv, d)) cand.push_back({kw, vv, d, 0});
     }
     if (scalar_variant_available(ctx->prob.itype, ctx->pol, K_TBLOCK_IL, v)) {
       for (int d : {16, 32, 64, 128}) {

@@ -19,7 +19,9 @@ enum : int {
   K_TBLOCK_B2 = 3,  // workgroup tiles of 2, 4 or 8 wavefronts
   K_TBLOCK_B4 = 4,
   K_TBLOCK_B8 = 5,
-  K_ND_MARCH = 6  // d-D grids: strips along axis 0 marching along the last axis
+  K_ND_MARCH = 6,  // d-D grids: strips along axis 0 marching along the last axis
+  K_TBLOCK_WG4 = 7,  // workgroup tiles of 4 or 8 wavefronts with overlapping windows
+  K_TBLOCK_WG8 = 8   // (int32 tables, periodic grids)
 };
 
 // Per-block partial results of the reduction kernel (one record per block).
@@ -41,6 +43,12 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
 bool scalar_variant_available(int itype, int pol, int kernel, int vec);
 int scalar_halo(int kernel, int vec, int ksteps);  // halo width of the temporal-blocking kernels
 int scalar_tile_positions(int kernel, int vec);     // cells loaded per tile
+
+// Workgroup tiles with overlapping wavefront windows (K_TBLOCK_WG4/8): int32
+// LUT policy, periodic grids, vec 2 or 4, ksteps up to 64*vec - 16.
+bool tblock_wg_valid(int nw, int vec, int ksteps);
+hipError_t launch_tblock_wg(int nw, int vec, const int32_t* src, int32_t* dst, int64_t n,
+                            int ksteps, const XParams& P, hipStream_t s);
 
 // FP64 split finite-volume twin (state u in doubles).
 bool classical_variant_available(int pol, int kernel, int vec);

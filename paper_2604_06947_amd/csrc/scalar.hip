@@ -407,6 +407,141 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
 }
 
 // ---------------------------------------------------------------------------
+// K5: workgroup tiles with overlapping wavefront windows (int32 tables,
+// periodic grids).  The NW wavefronts of a workgroup hold windows of 64*V
+// cells that overlap their neighbours by 2*WG_H cells; every WG_H steps each
+// wavefront refreshes the WG_H cells at each end of its window from the
+// neighbour's cells that are still valid there (LDS, double-buffered, one
+// barrier per refresh).  Only the workgroup's two outer ends pay the deep halo
+// of `khalo` >= ksteps cells, so about 1 - 2*khalo/(NW*64*V) of the work is
+// stored instead of 1 - 2*khalo/(64*V).  The table slice the tile can reach is
+// shared by the workgroup; cells are carried as their slice addresses.
+// ---------------------------------------------------------------------------
+constexpr int WG_H = 8;       // refresh period, and half the overlap of two windows
+constexpr int WG_WIN = 2048;  // table entries one workgroup can stage
+
+template <int V>
+__device__ __forceinline__ void wg_load(const int32_t* __restrict__ p, int32_t (&q)[V]) {
+  if constexpr (V == 2) {
+    typedef int v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *reinterpret_cast<const v2*>(p);
+    q[0] = v[0];
+    q[1] = v[1];
+  } else {
+    load_vec<int32_t, V>(p, q);
+  }
+}
+
+template <int V, int NW>
+__global__ __launch_bounds__(NW * 64) void k_tblock_wg(const int32_t* __restrict__ src,
+                                                       int32_t* __restrict__ dst, int64_t n,
+                                                       int ksteps, int khalo, XParams P) {
+  constexpr int W = 64 * V;
+  constexpr int WTOT = NW * W - (NW - 1) * 2 * WG_H;
+  __shared__ int2 s_win[WG_WIN];
+  __shared__ uint32_t s_xch[2][NW][2][WG_H];
+  __shared__ int32_t s_mn[NW], s_mx[NW];
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int64_t TS = WTOT - 2 * khalo;  // cells stored per workgroup
+  const int64_t S = xcd_tile(blockIdx.x, gridDim.x) * TS - khalo;
+  const int64_t g0 = S + wave * (W - 2 * WG_H) + lane * V;
+  const bool inside = S >= 0 && S + WTOT <= n;  // uniform over the workgroup
+  int32_t q[V];
+  if (inside) {
+    wg_load<V>(src + g0, q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = src[wrap_index(g0 + j, n)];
+  }
+  // range of the tile's initial states
+  int32_t mn = q[0], mx = q[0];
+#pragma unroll
+  for (int j = 1; j < V; ++j) {
+    mn = q[j] < mn ? q[j] : mn;
+    mx = q[j] > mx ? q[j] : mx;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int32_t a = __shfl_xor(mn, off, 64), b = __shfl_xor(mx, off, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) {
+    s_mn[wave] = mn;
+    s_mx[wave] = mx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    mn = s_mn[w] < mn ? s_mn[w] : mn;
+    mx = s_mx[w] > mx ? s_mx[w] : mx;
+  }
+  const int64_t span = static_cast<int64_t>(mx) - mn;
+  const LutView L = lut_view(P);
+  // Exchange the window ends with the neighbouring wavefronts: a wavefront
+  // sends its cells at positions [WG_H, 2*WG_H) and [W - 2*WG_H, W - WG_H)
+  // (position = lane*V + j) and receives [0, WG_H) and [W - WG_H, W).  The
+  // buffer alternates between refreshes, so one barrier per refresh suffices.
+  auto refresh = [&](auto (&x)[V], int par) {
+    using T = typename std::remove_reference<decltype(x[0])>::type;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int p = lane * V + j;
+      if (p >= WG_H && p < 2 * WG_H) s_xch[par][wave][0][p - WG_H] = static_cast<uint32_t>(x[j]);
+      if (p >= W - 2 * WG_H && p < W - WG_H)
+        s_xch[par][wave][1][p - (W - 2 * WG_H)] = static_cast<uint32_t>(x[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int p = lane * V + j;
+      if (wave > 0 && p < WG_H) x[j] = static_cast<T>(s_xch[par][wave - 1][1][p]);
+      if (wave < NW - 1 && p >= W - WG_H) x[j] = static_cast<T>(s_xch[par][wave + 1][0][p - (W - WG_H)]);
+    }
+  };
+  if (span < WG_WIN) {  // uniform over the workgroup
+    for (int i = threadIdx.x; i <= span; i += NW * 64) {
+      const uint32_t off =
+          (static_cast<uint32_t>(mn) + static_cast<uint32_t>(i) - static_cast<uint32_t>(P.lut_lo))
+          << 3;
+      const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
+      s_win[i] = make_int2(e[0], e[1]);
+    }
+    __syncthreads();
+    const uint32_t base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(s_win)));
+    const uint32_t end = base + (static_cast<uint32_t>(span) << 3);
+    uint32_t a[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(mn)) << 3);
+    for (int s = 0; s < ksteps; ++s) {
+      tb_step_addr<V>(a, end);
+      if ((s + 1) % WG_H == 0 && s + 1 < ksteps) refresh(a, ((s + 1) / WG_H) & 1);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      q[j] = static_cast<int32_t>(static_cast<uint32_t>(mn) +
+                                  static_cast<uint32_t>(static_cast<int32_t>(a[j] - base) >> 3));
+  } else {
+    const LdsWindow Wn{0u, 0u};
+    long long led = 0;
+    for (int s = 0; s < ksteps; ++s) {
+      tb_step<int32_t, P_LUT, V, false>(P, L, Wn, q, g0, n, false, led);
+      if ((s + 1) % WG_H == 0 && s + 1 < ksteps) refresh(q, ((s + 1) / WG_H) & 1);
+    }
+  }
+  // this wavefront's share of the stored cells
+  const int lo_p = wave == 0 ? khalo : WG_H;
+  const int hi_p = wave == NW - 1 ? W - khalo : W - WG_H;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int p = lane * V + j;
+    if (p >= lo_p && p < hi_p && g0 + j < n) dst[g0 + j] = q[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K4: temporal blocking with a workgroup tile.  The NW wavefronts of a
 // workgroup hold one contiguous tile of NW*64*V cells (V per lane, lanes in
 // order), so the halo is paid once per workgroup instead of once per
@@ -954,6 +1089,29 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
   if (itype == FQNM_I32)
     return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
   return by_pol<int64_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+}
+
+int tblock_wg_positions(int nw, int vec) { return nw * 64 * vec - (nw - 1) * 2 * WG_H; }
+
+bool tblock_wg_valid(int nw, int vec, int ksteps) {
+  if ((nw != 4 && nw != 8) || (vec != 2 && vec != 4) || ksteps < 1) return false;
+  const int kh = scalar_halo(K_TBLOCK, vec, ksteps);
+  return kh <= 64 * vec - 2 * WG_H && tblock_wg_positions(nw, vec) - 2 * kh > 0;
+}
+
+hipError_t launch_tblock_wg(int nw, int vec, const int32_t* src, int32_t* dst, int64_t n,
+                            int ksteps, const XParams& P, hipStream_t s) {
+  if (!tblock_wg_valid(nw, vec, ksteps)) return hipErrorInvalidValue;
+  const int kh = scalar_halo(K_TBLOCK, vec, ksteps);
+  const int64_t ts = tblock_wg_positions(nw, vec) - 2 * kh;
+  const int64_t blocks = (n + ts - 1) / ts;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 g(static_cast<unsigned>(blocks));
+  if (nw == 4 && vec == 2) k_tblock_wg<2, 4><<<g, 256, 0, s>>>(src, dst, n, ksteps, kh, P);
+  else if (nw == 4) k_tblock_wg<4, 4><<<g, 256, 0, s>>>(src, dst, n, ksteps, kh, P);
+  else if (vec == 2) k_tblock_wg<2, 8><<<g, 512, 0, s>>>(src, dst, n, ksteps, kh, P);
+  else k_tblock_wg<4, 8><<<g, 512, 0, s>>>(src, dst, n, ksteps, kh, P);
+  return hipGetLastError();
 }
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,

@@ -35,6 +35,7 @@ EVAL_AUTO, EVAL_DIRECT, EVAL_LUT = 0, 1, 2
 KERNEL_STREAM, KERNEL_TBLOCK, KERNEL_TBLOCK_IL = 0, 1, 2
 KERNEL_TBLOCK_B2, KERNEL_TBLOCK_B4, KERNEL_TBLOCK_B8 = 3, 4, 5
 KERNEL_ND_MARCH = 6
+KERNEL_TBLOCK_WG4, KERNEL_TBLOCK_WG8 = 7, 8
 
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",

@@ -279,6 +279,70 @@ def test_w2_burgers_full_size_sampled():
         assert q[i] == window_centre(op, q0, int(i), w.steps), i
 
 
+# Workgroup tiles with overlapping wavefront windows (int32 tables, periodic):
+# depths below, at and above the refresh period, the largest allowed depth,
+# a step count that ends on a partial pass; grids smaller than one window,
+# one workgroup, several workgroups with a ragged tail; and states whose tile
+# range is too wide for the shared table slice (the global-table path).
+WG_PLANS = [(F.KERNEL_TBLOCK_WG4, 2, 5), (F.KERNEL_TBLOCK_WG4, 2, 8), (F.KERNEL_TBLOCK_WG4, 4, 48),
+            (F.KERNEL_TBLOCK_WG8, 2, 24), (F.KERNEL_TBLOCK_WG8, 4, 96), (F.KERNEL_TBLOCK_WG4, 2, 112),
+            (F.KERNEL_TBLOCK_WG8, 4, 17), (F.KERNEL_TBLOCK_WG4, 4, 240)]
+
+
+@pytest.mark.parametrize("flux,a", [(F.FLUX_UPWIND, 1.0), (F.FLUX_UPWIND, -0.9),
+                                    (F.FLUX_BURGERS_EO, 1.0)])
+@pytest.mark.parametrize("n,amp", [(1, 1.0), (7, 1.0), (130, 1.0), (1000, 1.0), (5003, 1.0),
+                                   (40000, 0.02), (40000, 1.0)])
+def test_overlapping_window_tiles(flux, a, n, amp):
+    u0, prob = make_case(flux, F.BC_PERIODIC, F.I32, n, seed=300 + n, a=a, lut=True)
+    u0 = u0 * amp
+    op = oracle_problem(prob)
+    q0 = O.quantise(u0, prob.delta, 32)
+    steps = 251
+    ref = O.step(op, q0, steps)
+    for plan in WG_PLANS:
+        q, inv = gpu_run(prob, q0=q0.astype(np.int32), steps=steps, plan=plan)
+        assert np.array_equal(q, ref), plan
+        assert inv["sum"][0] == int(q0.sum())
+
+
+def test_overlapping_window_tiles_refused_elsewhere():
+    for bc, lut, itype in [(F.BC_OUTFLOW, True, F.I32), (F.BC_PERIODIC, False, F.I32),
+                           (F.BC_PERIODIC, True, F.I64)]:
+        u0, prob = make_case(F.FLUX_BURGERS_EO, bc, itype, 300, seed=1, lut=lut)
+        h = F.fqnm_create_from_field(prob, u0)
+        try:
+            with pytest.raises(F.FqnmError):
+                F.fqnm_set_plan(h, F.KERNEL_TBLOCK_WG4, 4, 48)
+        finally:
+            F.fqnm_destroy(h)
+    u0, prob = make_case(F.FLUX_BURGERS_EO, F.BC_PERIODIC, F.I32, 300, seed=1, lut=True)
+    h = F.fqnm_create_from_field(prob, u0)
+    try:
+        for bad in [(F.KERNEL_TBLOCK_WG4, 8, 48), (F.KERNEL_TBLOCK_WG8, 2, 113)]:
+            with pytest.raises(F.FqnmError):
+                F.fqnm_set_plan(h, *bad)
+    finally:
+        F.fqnm_destroy(h)
+
+
+def test_w2_full_size_overlapping_windows_sampled():
+    w = W.w2_burgers_step()
+    prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
+                          eval_=F.EVAL_LUT)
+    q0 = O.quantise(w.u0, w.delta, 32)
+    op = O.Problem(O.BURGERS_EO, w.delta, w.lam, width=32)
+    xs = int(np.argmax(np.diff(q0) > 10000))  # near the seeded step
+    rng = np.random.default_rng(2025)
+    pts = [0, w.n - 1, xs, xs + 1] + list(rng.integers(0, w.n, 2))
+    refs = {i: window_centre(op, q0, int(i), w.steps) for i in pts}
+    for plan in [(F.KERNEL_TBLOCK_WG8, 4, 96), (F.KERNEL_TBLOCK_WG4, 2, 64)]:
+        q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
+        assert inv["sum"][0] == int(q0.sum())
+        for i in pts:
+            assert q[i] == refs[i], (plan, i)
+
+
 @pytest.mark.parametrize("r", [1e-2, 1e-3, 1e-4])
 def test_w3_nyquist_full_size_sampled(r):
     from paper_2604_06947_amd import plans
