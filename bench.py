@@ -394,6 +394,47 @@ def cpu_oracle_rate(w, steps):
     return w.n * steps / dt, dt
 
 
+def copy_ceiling(reps=5):
+    """Device-to-device copy of 1 GiB (torch, HIP events): the practical HBM
+    ceiling on this machine, read + write bytes per second."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    t = float(np.median(ts))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"device_copy_GBps": 2.0 * n / t / 1e9, "frac_of_hbm_peak": 2.0 * n / t / 1e9 / HBM_PEAK_GBS}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
 def copy_probe():
     import torch
     n = 256 << 20
@@ -535,15 +576,20 @@ def main():
     # ---------------- level statistics (entropy, transitions) -------------------------
     if not args.no_extras and args.only in ("", "levels"):
         extras.update(bench_levels(F, W, stream))
+    # ---------------- the device-copy ceiling of the box ------------------------------
+    if not args.no_extras and args.only in ("",):
+        extras["copy_ceiling"] = copy_ceiling()
     # ---------------- CPU oracle baseline --------------------------------------------
     if not args.no_cpu:
         csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "600"))
         log(f"[bench] cpu oracle sample: {w.n} cells x {csteps} steps")
         rate, dt = cpu_oracle_rate(w, csteps)
+        model, avail = host_cpu()
         out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"burgers-eo 2^20 int32 cells x {csteps} of the "
-                                         f"10000 steps, single-threaded C oracle, {dt:.1f} s"}
+                                         f"10000 steps, single-threaded C oracle, {dt:.1f} s, "
+                                         f"on {model} ({avail} cores available)"}
     if extras:
         out["extras"] = extras
     print(json.dumps(out), flush=True)

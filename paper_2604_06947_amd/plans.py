@@ -15,9 +15,9 @@ STREAM_PLAN_W3 = (KERNEL_STREAM, 2, 1)
 # Valid only for the kernel sources they were measured on: the benchmark
 # reports null when the hash of those sources differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
-MEASURED_SOURCES_SHA = "336835e8e3cb3f92"
+MEASURED_SOURCES_SHA = "a1ff69a8f8df1921"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "w2": 11495 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
+    "w2": 11507 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
     "w6": 144734 * 1024,  # k_nd_march<int, P_EO, 8, 2>, 12 rows per wavefront, one step
 }
 ND_KERNEL_SOURCES = ("csrc/nd.hip", "csrc/fqnm_device.h")
