@@ -127,6 +127,8 @@ struct Marcher {
   int64_t yl, yr;      // 3-D: offsets of the neighbouring rows of the middle axis
   int lane;
   bool vec_row;
+  bool same_m;  // the marching axis has axis 0's map constants: its maps are axis 0's
+  bool same_y;  // 3-D: the same for the middle axis
 
   __device__ __forceinline__ void load_row(const IT* __restrict__ row, IT (&q)[V]) const {
     if (vec_row) {
@@ -168,9 +170,16 @@ struct Marcher {
     if constexpr (NdSplit<POL>::value) {
       IT ppx[V], pmx[V];
 #pragma unroll
-      for (int k = 0; k < V; ++k) {
-        axis_maps<IT, POL>(AX, S.q[k], ppx[k], pmx[k]);
-        axis_maps<IT, POL>(P.ax[DIM - 1], S.q[k], R.ppm[k], pmm[k]);
+      for (int k = 0; k < V; ++k) axis_maps<IT, POL>(AX, S.q[k], ppx[k], pmx[k]);
+      if (same_m) {  // uniform
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          R.ppm[k] = ppx[k];
+          pmm[k] = pmx[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) axis_maps<IT, POL>(P.ax[DIM - 1], S.q[k], R.ppm[k], pmm[k]);
       }
       IT gp, gm, hp, hm;
       axis_maps<IT, POL>(AX, S.gl, gp, gm);
@@ -211,7 +220,11 @@ struct Marcher {
           IT pl, ml, pr, mr, pq, mq;
           axis_maps<IT, POL>(AY, S.ql[k], pl, ml);
           axis_maps<IT, POL>(AY, S.qr[k], pr, mr);
-          axis_maps<IT, POL>(AY, S.q[k], pq, mq);
+          if (same_y) {  // uniform
+            axis_maps<IT, POL>(AX, S.q[k], pq, mq);  // shares the axis-0 evaluation above
+          } else {
+            axis_maps<IT, POL>(AY, S.q[k], pq, mq);
+          }
           lo = pl + mq;
           hi = pq + mr;
         } else {
@@ -276,6 +289,12 @@ __global__ __launch_bounds__(256) void k_nd_march(const IT* __restrict__ src, IT
     M.nvalid = static_cast<int32_t>(left < 0 ? 0 : (left > V ? V : left));
     M.klast = left >= 1 && left <= V ? static_cast<int32_t>(left - 1) : -1;
   }
+  auto same = [](const NdAxis& a, const NdAxis& b) {
+    return a.x.c == b.x.c && a.x.h == b.x.h && a.x.a == b.x.a && a.x.alpha == b.x.alpha &&
+           a.x.delta == b.x.delta && a.x.lambda == b.x.lambda;
+  };
+  M.same_m = same(AX, AM);
+  M.same_y = DIM == 3 && same(AX, P.ax[1]);
   M.yl = M.yr = 0;
   if constexpr (DIM == 3) {
     M.yl = nd_ghost(M.y - 1, M.ny, P.ax[1].bc) * M.nx;
@@ -311,25 +330,28 @@ __global__ __launch_bounds__(256) void k_nd_march(const IT* __restrict__ src, IT
   // so two positions are always in flight.  Positions up to jend are needed
   // (jend for the flux of the last row's upper face).
   long long led = 0;
-  auto row = [&](int64_t j, Stage<IT, V, DIM>& S) {
+  // cur = row j, nxt = row j + 1 (with its phi- along the marching axis); after
+  // row j is finished, cur's registers take position j + 2, so the two buffers
+  // trade roles every row instead of being copied
+  auto row = [&](int64_t j, Stage<IT, V, DIM>& S, Ready<IT, V>& cur, Ready<IT, V>& nxt,
+                 IT (&pmm_nxt)[V], IT (&pmm_cur)[V]) {
     const int64_t off = M.base + j * M.SM;
     IT out[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       IT FMhi;
-      if constexpr (NdSplit<POL>::value) FMhi = rb.ppm[k] + pmm_c[k];
-      else FMhi = transfer<IT, POL>(AM.x, rb.q[k], rc.q[k]);
-      out[k] = wsub<IT>(wsub<IT>(rb.q[k], rb.d[k]), wsub<IT>(FMhi, FMlo[k]));
+      if constexpr (NdSplit<POL>::value) FMhi = cur.ppm[k] + pmm_nxt[k];
+      else FMhi = transfer<IT, POL>(AM.x, cur.q[k], nxt.q[k]);
+      out[k] = wsub<IT>(wsub<IT>(cur.q[k], cur.d[k]), wsub<IT>(FMhi, FMlo[k]));
       if (AM.bc == FQNM_BC_OUTFLOW && (j == 0 || j == M.nm - 1) && k < M.nvalid) {  // uniform
         if (j == 0) led += static_cast<long long>(FMlo[k]);
         if (j == M.nm - 1) led -= static_cast<long long>(FMhi);
       }
       FMlo[k] = FMhi;
     }
-    led += rb.led;
-    rb = rc;
+    led += cur.led;
     if (j + 2 <= jend) {  // uniform
-      M.process(S, rc, pmm_c);
+      M.process(S, cur, pmm_cur);
       if (j + 4 <= jend) M.load(j + 4, S);
     }
     if (M.vec_row) {
@@ -341,8 +363,8 @@ __global__ __launch_bounds__(256) void k_nd_march(const IT* __restrict__ src, IT
     }
   };
   for (int64_t j = j0; j < jend; j += 2) {
-    row(j, S0);
-    if (j + 1 < jend) row(j + 1, S1);
+    row(j, S0, rb, rc, pmm_c, pmm_b);
+    if (j + 1 < jend) row(j + 1, S1, rc, rb, pmm_b, pmm_c);
   }
   if (led != 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
