@@ -154,9 +154,11 @@ const char* fqnm_version(void);
 
 /* Create a solver from an integer initial state q0_host (n or 3n integers of
  * the problem's itype; for the density-only Euler kinds 3n 8-byte slots: n
- * int64 density counts, then n FP64 momenta and n FP64 energies).  Validates the problem: positive finite delta, dx,
- * lambda (FQNM_ERR_ARG); the CFL number over [min q0, max q0] for scalar
- * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^52 so that q converts
+ * int64 density counts, then n FP64 momenta and n FP64 energies).  Validates
+ * the problem: positive finite delta, dx, lambda (FQNM_ERR_ARG); the CFL
+ * number over [min q0, max q0] for scalar
+ * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^52 (2^51 for int64
+ * scalar kinds, whose maps convert through a 1.5*2^52 bias) so that q converts
  * to FP64 exactly, q^2 < 2^53 for Burgers kinds, and for I32 that
  * |q| + 2 max|F| < 2^31 on that range (FQNM_ERR_RANGE).  Copies q0 to the
  * device on hip_stream and builds the LUT when the eval mode asks for it. */

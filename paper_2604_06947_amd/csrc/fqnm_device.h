@@ -40,14 +40,35 @@ struct XParams {
   int64_t lut_last; // number of entries - 1
 };
 
+// For 64-bit states the conversions use the bias B = 1.5*2^52: for |v| < 2^51
+// the double B + v has the integer v in its low mantissa bits, so
+// int64 -> double is one integer add and one FP subtraction, both exact, and
+// rounding x to an integer is the FP addition x + B, which rounds half to even
+// like rint.  States and map values of 64-bit contexts are validated below
+// 2^51 in magnitude (map values are at most |q| under the CFL condition); a
+// discarded halo lane holding anything else gets a meaningless, never stored,
+// value.  32-bit states use the single hardware conversions.
+constexpr int64_t F64_BIAS_BITS = 0x4338000000000000LL;  // 1.5*2^52
+constexpr double F64_BIAS = 6755399441055744.0;          // 1.5*2^52
+
 template <typename IT>
 __device__ __forceinline__ IT round_to(double x) {
-  return static_cast<IT>(rint(x));
+  if constexpr (sizeof(IT) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x + F64_BIAS);
+    return static_cast<IT>(b - static_cast<uint64_t>(F64_BIAS_BITS));
+  } else {
+    return static_cast<IT>(rint(x));
+  }
 }
 
 template <typename IT>
 __device__ __forceinline__ double as_f64(IT q) {
-  return static_cast<double>(q);
+  if constexpr (sizeof(IT) == 8) {
+    const uint64_t b = static_cast<uint64_t>(F64_BIAS_BITS) + static_cast<uint64_t>(q);
+    return __builtin_bit_cast(double, b) - F64_BIAS;
+  } else {
+    return static_cast<double>(q);
+  }
 }
 
 // s*s for a state s with s^2 < 2^53 (validated at create): the FP64 product of
