@@ -47,17 +47,20 @@ struct XParams {
 // like rint.  States and map values of 64-bit contexts are validated below
 // 2^51 in magnitude (map values are at most |q| under the CFL condition); a
 // discarded halo lane holding anything else gets a meaningless, never stored,
-// value.  32-bit states use the single hardware conversions.
+// value.  32-bit states convert with the hardware instruction and round with
+// the same bias addition.
 constexpr int64_t F64_BIAS_BITS = 0x4338000000000000LL;  // 1.5*2^52
 constexpr double F64_BIAS = 6755399441055744.0;          // 1.5*2^52
 
 template <typename IT>
 __device__ __forceinline__ IT round_to(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x + F64_BIAS);
   if constexpr (sizeof(IT) == 8) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x + F64_BIAS);
     return static_cast<IT>(b - static_cast<uint64_t>(F64_BIAS_BITS));
   } else {
-    return static_cast<IT>(rint(x));
+    // the bias has a zero low word: the low 32 bits are the rounded integer
+    // (map values of 32-bit states are validated to fit int32)
+    return static_cast<IT>(static_cast<uint32_t>(b));
   }
 }
 
