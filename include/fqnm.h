@@ -157,8 +157,8 @@ const char* fqnm_version(void);
  * int64 density counts, then n FP64 momenta and n FP64 energies).  Validates
  * the problem: positive finite delta, dx, lambda (FQNM_ERR_ARG); the CFL
  * number over [min q0, max q0] for scalar
- * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^52 (2^51 for int64
- * scalar kinds, whose maps convert through a 1.5*2^52 bias) so that q converts
+ * kinds (FQNM_ERR_CFL, Sec. 2.2 eq:cfl_number); |q| < 2^51 for int64 states
+ * (the transfers convert through a 1.5*2^52 bias) so that q converts
  * to FP64 exactly, q^2 < 2^53 for Burgers kinds, and for I32 that
  * |q| + 2 max|F| < 2^31 on that range (FQNM_ERR_RANGE).  Copies q0 to the
  * device on hip_stream and builds the LUT when the eval mode asks for it. */

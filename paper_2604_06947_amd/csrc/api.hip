@@ -146,10 +146,10 @@ static fqnm_status cfl_fail(double nu) {
 fqnm_status validate_range(const fqnm_problem& p, int64_t lo, int64_t hi) {
   const double qa = std::max(std::fabs((double)lo), std::fabs((double)hi));
   if (qa >= 4503599627370496.0) return fail(FQNM_ERR_RANGE, "|q| must stay below 2^52");
-  if (is_euler(p.flux)) return FQNM_OK;
-  // the transfer maps of 64-bit states convert through the 1.5*2^52 bias
+  // the transfers of 64-bit states convert through the 1.5*2^52 bias
   if (p.itype == FQNM_I64 && qa >= 2251799813685248.0)
-    return fail(FQNM_ERR_RANGE, "|q| must stay below 2^51 for int64 scalar kinds");
+    return fail(FQNM_ERR_RANGE, "|q| must stay below 2^51 for int64 states");
+  if (is_euler(p.flux)) return FQNM_OK;
   if (is_burgers(p.flux) && qa > 94906265.0)
     return fail(FQNM_ERR_RANGE, "Burgers kinds need q^2 < 2^53 (|q| <= 94906265)");
   double nu = 0.0;

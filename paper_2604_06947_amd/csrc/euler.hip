@@ -75,11 +75,11 @@ __device__ __forceinline__ Prim cell_primitives_f(const EulerParams& E, double r
 // density counts with FP64 m and E.
 __device__ __forceinline__ Prim cell_primitives(const EulerParams& E, int64_t qr, int64_t qm,
                                                 int64_t qE) {
-  const double r = E.delta * static_cast<double>(qr);
+  const double r = E.delta * as_f64<int64_t>(qr);
   if (E.dens)
     return cell_primitives_f(E, r, __builtin_bit_cast(double, qm), __builtin_bit_cast(double, qE));
-  const double m = E.delta * static_cast<double>(qm);
-  const double en = E.delta * static_cast<double>(qE);
+  const double m = E.delta * as_f64<int64_t>(qm);
+  const double en = E.delta * as_f64<int64_t>(qE);
   return cell_primitives_f(E, r, m, en);
 }
 
@@ -173,7 +173,7 @@ __device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L
     } else {
       double v = F * E.lambda;
       v = v / E.delta;
-      T[c] = static_cast<int64_t>(rint(v));
+      T[c] = round_to<int64_t>(v);  // |v| < 2^51: counts are validated below 2^51
     }
   }
 }
