@@ -15,13 +15,13 @@ STREAM_PLAN_W3 = (KERNEL_STREAM, 2, 1)
 # Valid only for the kernel sources they were measured on: the benchmark
 # reports null when the hash of those sources differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
-MEASURED_SOURCES_SHA = "a1ff69a8f8df1921"
+MEASURED_SOURCES_SHA = "eca8c61d964590e8"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "w2": 11507 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
-    "w6": 144734 * 1024,  # k_nd_march<int, P_EO, 8, 2>, 12 rows per wavefront, one step
+    "w2": 11503 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
+    "w6": 144719 * 1024,  # k_nd_march<int, P_EO, 8, 2>, 12 rows per wavefront, one step
 }
 ND_KERNEL_SOURCES = ("csrc/nd.hip", "csrc/fqnm_device.h")
-ND_MEASURED_SOURCES_SHA = "f1ac9e349f35c7fc"
+ND_MEASURED_SOURCES_SHA = "b2a7aa91e2d37265"
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery
 TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
