@@ -477,8 +477,8 @@ def run_extras_only(args, F, W, plans, stream):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(instances and grids shard across GPUs by design but no multi-GPU path is built)",
+        print("bench.py: the library drives one GPU; --gpus must be 1 "
+              "(instances and grids shard across GPUs by design, but no multi-GPU path exists)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -53,7 +53,7 @@ typedef enum {
   FQNM_ERR_DEVICE = -5,      /* HIP runtime error (sticky for the object)                         */
   FQNM_ERR_STATE = -6,       /* call not valid in the object's current state                      */
   FQNM_ERR_BUSY = -7,        /* resource temporarily unavailable (server queue full)              */
-  FQNM_ERR_UNSUPPORTED = -8  /* valid request that this build does not implement                  */
+  FQNM_ERR_UNSUPPORTED = -8  /* valid request that the library does not implement                 */
 } fqnm_status;
 
 /* Flux kinds.  Split kinds round f+ and f- separately (eq:flux_table); two-point
