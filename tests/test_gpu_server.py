@@ -129,3 +129,58 @@ def test_oversize_request_refused():
         assert e.value.status == F.ERR_OOM
     finally:
         F.fqnm_server_destroy(srv)
+
+
+def test_w5_request_set_as_benchmarked():
+    """The served Sod request set at the size, device budget and tick the
+    benchmark runs it with.  Every request with N <= 2048 and a seeded sample
+    of larger ones equal the oracle; every request equals the same request
+    advanced alone by the single-grid stepper, whose invariants close the mass
+    balance of each component through the outflow ledger."""
+    import bench
+    reqs = W.w5_sod_requests(count=bench.SERVE_COUNT, nmax=bench.SERVE_NMAX)
+    items = []
+    for r in reqs:
+        q0 = np.stack([O.quantise(r.U0[c], r.delta, 64) for c in range(3)])
+        prob = F.make_problem(r.kind, r.delta, r.lam, r.n, bc=F.BC_OUTFLOW, itype=F.I64,
+                              gamma=r.gamma)
+        items.append((prob, q0, r.steps, r))
+    # the device quantiser the benchmark uses gives the same integers
+    for prob, q0, _, r in items[:8]:
+        assert np.array_equal(F.fqnm_quantise(r.U0.ravel(), r.delta, F.I64), q0.ravel())
+    srv = F.fqnm_server_create(bench.SERVE_BUDGET, 64)
+    outs = [np.empty(q0.size, np.int64) for _, q0, _, _ in items]
+    try:
+        for (prob, q0, steps, _), out in zip(items, outs):
+            F.fqnm_server_submit(srv, prob, q0.ravel(), steps, out)
+        F.fqnm_server_drain(srv, 300.0)
+        comps = []
+        while True:
+            c = F.fqnm_server_poll(srv, 256)
+            if not c:
+                break
+            comps += c
+        stats = F.fqnm_server_stats_get(srv)
+    finally:
+        F.fqnm_server_destroy(srv)
+    assert len(comps) == len(items) and all(c["status"] == 0 for c in comps)
+    assert stats["peak_bytes"] <= bench.SERVE_BUDGET
+    ns = np.array([p.n for p, _, _, _ in items])
+    large = np.flatnonzero((ns > 2048) & (ns <= 8192))
+    pick = set(np.flatnonzero(ns <= 2048).tolist())
+    pick |= set(np.random.default_rng(505).choice(large, size=3, replace=False).tolist())
+    for k in sorted(pick):
+        prob, q0, steps, r = items[k]
+        op = O.Problem(r.kind, r.delta, r.lam, bc=O.OUTFLOW, width=64, gamma=r.gamma)
+        assert np.array_equal(outs[k].reshape(3, -1), O.step_euler(op, q0, steps)), (k, prob.n)
+    for (prob, q0, steps, _), out in zip(items, outs):
+        h = F.fqnm_create(prob, q0.ravel())
+        try:
+            F.fqnm_step(h, steps)
+            alone = F.fqnm_get_state(h, prob)
+            inv = F.fqnm_invariants_get(h)
+        finally:
+            F.fqnm_destroy(h)
+        assert np.array_equal(alone.ravel(), out), prob.n
+        for c in range(3):
+            assert inv["sum"][c] == int(q0[c].sum()) + inv["ledger"][c], (prob.n, c)
