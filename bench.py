@@ -268,46 +268,60 @@ def bench_serve(F, W, stream):
 
 def bench_nd(F, W, plans, stream, reps=3):
     """W6: 2-D Burgers by directional composition, 4096 x 4096 int32 cells,
-    1000 steps, one step per launch of the marching kernel; device time of
-    the whole solve by HIP events on the library's stream (the state is
-    uploaded before the timer)."""
+    1000 steps; the marching kernel with temporal blocking (several steps per
+    launch), and the one-step-per-launch marching kernel beside it.  Device
+    time of the whole solve by HIP events on the library's stream (the state
+    is uploaded before the timer)."""
     import torch
     w = W.w6_burgers_2d()
     ny, nx = w.shape
+    cells = nx * ny
     q0 = F.fqnm_quantise(w.u0.ravel(), w.delta, F.I32, stream).reshape(w.shape)
     axes = [F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam[m], (nx, ny)[m], itype=F.I32)
             for m in range(2)]
-    ts = []
-    for _ in range(reps + 1):
-        h = F.fqnm_create_nd(axes, q0, stream)
-        F.fqnm_set_plan(h, F.KERNEL_ND_MARCH, *plans.ND_PLAN_W6)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(torch.cuda.current_stream())
-        F.fqnm_step(h, w.steps)
-        e1.record(torch.cuda.current_stream())
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e-3)
-        inv = F.fqnm_invariants_get(h)
-        F.fqnm_destroy(h)
-    t = float(np.median(ts[1:]))
-    cells = nx * ny
+
+    def solve(kernel, vec, depth):
+        ts, inv = [], None
+        for _ in range(reps + 1):
+            h = F.fqnm_create_nd(axes, q0, stream)
+            F.fqnm_set_plan(h, kernel, vec, depth)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            F.fqnm_step(h, w.steps)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+            inv = F.fqnm_invariants_get(h)
+            F.fqnm_destroy(h)
+        return float(np.median(ts[1:])), inv
+
+    kern, vec, K, rows = plans.ND_PLAN_W6
+    assert w.steps % K == 0
+    t, inv = solve(kern, vec, F.nd_tb_depth(K, rows))
+    launches = w.steps // K
     rate = cells * w.steps / t
-    ach = 8.0 * cells / (t / w.steps) / 1e9
-    log(f"[bench] W6 2-D {rate:.3e} cell-updates/s, {ach:.0f} GB/s algorithmic")
+    ach = 8.0 * cells * K / (t / launches) / 1e9
+    mv, mr = plans.ND_MARCH_PLAN_W6
+    t1, inv1 = solve(F.KERNEL_ND_MARCH, mv, mr)
+    log(f"[bench] W6 2-D {rate:.3e} cell-updates/s ({K} steps per launch), {ach:.0f} GB/s "
+        f"algorithmic; one step per launch {cells * w.steps / t1:.3e}")
+    measured = (kernel_sources_sha(plans.ND_KERNEL_SOURCES) == plans.ND_MEASURED_SOURCES_SHA
+                and plans.TRAFFIC_BYTES_PER_LAUNCH["w6"] is not None)
     return {"w6_burgers_2d": {
         "cells": cells, "shape": [ny, nx], "time_steps": w.steps, "cell_updates_per_s": rate,
-        "ms_per_solve": t * 1e3, "plan": list(plans.ND_PLAN_W6),
-        "kernel": "k_nd_march<int, P_EO, %d, 2>" % plans.ND_PLAN_W6[0],
+        "ms_per_solve": t * 1e3, "plan": {"vec": vec, "steps_per_launch": K, "rows": rows},
+        "kernel": "k_nd_tb<int, P_EO, %d, %d, true>" % (vec, K),
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "bytes_per_cell_update": 8,
-                     "traffic": (plans.TRAFFIC_BYTES_PER_LAUNCH["w6"]
-                                 if kernel_sources_sha(plans.ND_KERNEL_SOURCES)
-                                 == plans.ND_MEASURED_SOURCES_SHA
-                                 and tuple(plans.ND_PLAN_W6) == (8, 12) else None),
-                     "algorithmic_bytes_per_launch": 8 * cells,
-                     "avg_launch_us": t / w.steps * 1e6},
-        "conservation_ok": inv["sum"][0] == int(q0.astype(np.int64).sum())}}
+                     "traffic": plans.TRAFFIC_BYTES_PER_LAUNCH["w6"] if measured else None,
+                     "algorithmic_bytes_per_launch": 8 * cells * K,
+                     "avg_launch_us": t / launches * 1e6},
+        "one_step_per_launch": {"kernel": "k_nd_march<int, P_EO, %d, 2>" % mv, "rows": mr,
+                                "cell_updates_per_s": cells * w.steps / t1,
+                                "avg_launch_us": t1 / w.steps * 1e6},
+        "conservation_ok": inv["sum"][0] == int(q0.astype(np.int64).sum())
+        and inv1["sum"][0] == inv["sum"][0]}}
 
 
 def bench_euler(F, W, stream, n=1 << 20, steps=200, reps=3):

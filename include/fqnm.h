@@ -133,13 +133,17 @@ typedef struct {
  * advances it `depth` steps per pass over memory; 2 = temporal blocking with
  * lane-interleaved cells (consecutive cells in consecutive lanes, so table
  * reads coalesce), split kinds only; 3, 4, 5 = temporal blocking in
- * workgroup tiles of 2, 4 or 8 wavefronts; 6 = the d-D marching kernel (the
- * only one of d-D contexts): a wavefront owns 64*vec cells of axis 0 and
- * marches `depth` cells along the last axis, one step per pass; 7, 8 =
- * workgroup tiles of 4 or 8 wavefronts whose windows (64*vec cells, vec 2 or
- * 4) overlap by 16 cells and are refreshed from their neighbours every 8
- * steps, `depth` <= 64*vec - 16 steps per pass (int32 tables on periodic
- * grids only).  Zero fields mean "keep". */
+ * workgroup tiles of 2, 4 or 8 wavefronts; 6 = the d-D marching kernel: a
+ * wavefront owns 64*vec cells of axis 0 and marches `depth` cells along the
+ * last axis, one step per pass; 7, 8 = workgroup tiles of 4 or 8 wavefronts
+ * whose windows (64*vec cells, vec 2 or 4) overlap by 16 cells and are
+ * refreshed from their neighbours every 8 steps, `depth` <= 64*vec - 16 steps
+ * per pass (int32 tables on periodic grids only); 9 = d-D marching with
+ * temporal blocking (2-D int32 grids periodic on both axes, vec 2 or 4 dividing
+ * the length of axis 0): `depth & 0xFF` steps per pass (1, 2, 4 or 8; a
+ * remainder runs as smaller passes) and `depth >> 8` cells marched along
+ * axis 1 per wavefront (0 = chosen from the grid size).  d-D contexts run
+ * kernels 6 and 9 only.  Zero fields mean "keep". */
 typedef struct {
   int32_t kernel;
   int32_t vec;          /* cells per lane                                                */

@@ -388,16 +388,39 @@ static fqnm_status ctx_new(const fqnm_problem* prob, void* stream, fqnm_ctx** ou
   return FQNM_OK;
 }
 
-// Plan-cache key of a d-D context: dimension, kind, storage and the log2 of
-// each extent.
+// Plan-cache key of a d-D context: dimension, kind, storage, and the log2 of
+// each extent with its boundary kind.
 static std::string nd_plan_key(const fqnm_ctx* ctx) {
   std::string k = "nd" + std::to_string(ctx->dim) + "_" + plan_key(ctx->prob, ctx->pol);
   for (int m = 0; m < ctx->dim; ++m) {
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= ctx->nd.ax[m].n) ++lg;
-    k += "_" + std::to_string(lg);
+    k += "_" + std::to_string(lg) + "b" + std::to_string(ctx->nd.ax[m].bc);
   }
   return k;
+}
+
+// Temporal-blocking plans of d-D contexts keep the steps per pass in the low
+// 8 bits of `depth` and the rows per wavefront above them (0: chosen here so
+// that the launch has about six wavefronts per SIMD).
+static int nd_tb_depth(const fqnm_plan& pl) { return pl.depth & 0xFF; }
+static int nd_tb_rows(const fqnm_ctx* ctx, const fqnm_plan& pl) {
+  const int r = pl.depth >> 8;
+  if (r > 0) return r;
+  const int K = nd_tb_depth(pl), v = pl.vec;
+  const int64_t W = 64 * v - 2 * ((K + v - 1) / v * v);
+  const int64_t nstrips = (ctx->nd.ax[0].n + W - 1) / W;
+  const int64_t want = nstrips * ctx->nd.ax[1].n / (6 * 1024);
+  return static_cast<int>(std::max<int64_t>(8, std::min<int64_t>(64, want)));
+}
+static bool nd_plan_valid(const fqnm_ctx* ctx, const fqnm_plan& pl) {
+  if (pl.kernel == K_ND_TB) {
+    const int K = nd_tb_depth(pl);
+    return K >= 1 && nd_tb_step_depth(K) == K &&
+           nd_tb_valid(ctx->prob.itype, ctx->pol, pl.vec, ctx->nd);
+  }
+  return pl.kernel == K_ND_MARCH && pl.depth >= 1 &&
+         nd_variant_available(ctx->prob.itype, ctx->pol, pl.vec);
 }
 
 extern "C" {
@@ -525,9 +548,11 @@ fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0
   ctx->xp = ctx->nd.ax[0].x;
   ctx->pol = p0.flux == FQNM_FLUX_UPWIND ? P_UPWIND_POS : policy_of(p0, false);
   ctx->direct_pol = ctx->pol;
+  // 2-D int32 periodic grids default to 4 steps per pass, 2 cells per lane
   fqnm_plan pl{K_ND_MARCH, p0.itype == FQNM_I32 ? 4 : 2, 16, FQNM_EVAL_DIRECT};
+  if (nd_tb_valid(p0.itype, ctx->pol, 2, ctx->nd)) pl = fqnm_plan{K_ND_TB, 2, 4, FQNM_EVAL_DIRECT};
   fqnm_plan cached;
-  if (lookup_plan(nd_plan_key(ctx), &cached)) pl = cached;
+  if (lookup_plan(nd_plan_key(ctx), &cached) && nd_plan_valid(ctx, cached)) pl = cached;
   ctx->plan = pl;
   *out = ctx;
   return FQNM_OK;
@@ -604,6 +629,10 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
                              static_cast<double*>(dst), p.n, p.bc, static_cast<int>(k), khalo,
                              ctx->xp, ctx->stream);
       }
+    } else if (ctx->dim > 1 && pl.kernel == K_ND_TB) {
+      k = nd_tb_step_depth(static_cast<int>(std::min<int64_t>(nd_tb_depth(pl), left)));
+      e = launch_nd_tb(p.itype, ctx->pol, pl.vec, static_cast<int>(k), nd_tb_rows(ctx, pl), src,
+                       dst, ctx->nd, ctx->stream);
     } else if (ctx->dim > 1) {
       e = launch_nd(p.itype, ctx->pol, pl.vec, pl.depth, src, dst, ctx->nd, ctx->d_ledger,
                     ctx->stream);
@@ -790,13 +819,23 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (ctx->euler) return fail(FQNM_ERR_UNSUPPORTED, "Euler contexts have a fixed plan");
   fqnm_plan pl = ctx->plan;
   if (ctx->dim > 1) {
-    if (plan->kernel != 0 && plan->kernel != K_ND_MARCH)
-      return fail(FQNM_ERR_ARG, "d-D contexts run the marching kernel only");
+    if (plan->kernel != 0 && plan->kernel != K_ND_MARCH && plan->kernel != K_ND_TB)
+      return fail(FQNM_ERR_ARG, "d-D contexts run the marching kernels only");
+    if (plan->kernel) pl.kernel = plan->kernel;
     if (plan->vec) pl.vec = plan->vec;
     if (plan->depth) pl.depth = plan->depth;
-    if (!nd_variant_available(ctx->prob.itype, ctx->pol, pl.vec))
-      return fail(FQNM_ERR_ARG, "vec not available for this storage type");
-    if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth (rows per wavefront) must be >= 1");
+    if (pl.kernel == K_ND_TB) {
+      if (!nd_tb_valid(ctx->prob.itype, ctx->pol, pl.vec, ctx->nd))
+        return fail(FQNM_ERR_ARG, "temporal blocking needs a 2-D int32 grid, periodic on both "
+                                  "axes, vec 2 or 4 dividing the first axis");
+      const int K = nd_tb_depth(pl);
+      if (pl.depth < 1 || K < 1 || nd_tb_step_depth(K) != K)
+        return fail(FQNM_ERR_ARG, "steps per pass (depth & 0xFF) must be 1, 2, 4 or 8");
+    } else {
+      if (!nd_variant_available(ctx->prob.itype, ctx->pol, pl.vec))
+        return fail(FQNM_ERR_ARG, "vec not available for this storage type");
+      if (pl.depth < 1) return fail(FQNM_ERR_ARG, "depth (rows per wavefront) must be >= 1");
+    }
     ctx->plan = pl;
     return FQNM_OK;
   }
@@ -852,6 +891,10 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     for (int v : {2, 4, 8})
       if (nd_variant_available(ctx->prob.itype, ctx->pol, v))
         for (int r : {4, 8, 16, 32, 64}) cand.push_back({K_ND_MARCH, v, r, 0});
+    for (int v : {2, 4})
+      if (nd_tb_valid(ctx->prob.itype, ctx->pol, v, ctx->nd))
+        for (int K : {2, 4, 8})
+          for (int r : {0, 16, 32, 64}) cand.push_back({K_ND_TB, v, K | (r << 8), 0});
   }
   for (int v : (i32 ? vecs32 : vecs64)) {
     if (ctx->dim > 1) break;

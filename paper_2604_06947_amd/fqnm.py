@@ -36,6 +36,12 @@ KERNEL_STREAM, KERNEL_TBLOCK, KERNEL_TBLOCK_IL = 0, 1, 2
 KERNEL_TBLOCK_B2, KERNEL_TBLOCK_B4, KERNEL_TBLOCK_B8 = 3, 4, 5
 KERNEL_ND_MARCH = 6
 KERNEL_TBLOCK_WG4, KERNEL_TBLOCK_WG8 = 7, 8
+KERNEL_ND_TB = 9
+
+
+def nd_tb_depth(steps_per_pass, rows=0):
+    """`depth` of a KERNEL_ND_TB plan: steps per pass and rows per wavefront."""
+    return int(steps_per_pass) | (int(rows) << 8)
 
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",

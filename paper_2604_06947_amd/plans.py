@@ -18,13 +18,17 @@ KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
 MEASURED_SOURCES_SHA = "eca8c61d964590e8"
 TRAFFIC_BYTES_PER_LAUNCH = {
     "w2": 11503 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
-    "w6": 144719 * 1024,  # k_nd_march<int, P_EO, 8, 2>, 12 rows per wavefront, one step
+    "w6": 152936 * 1024,  # k_nd_tb<int, P_EO, 2, 4, true>, 24 rows per wavefront, 4 steps
 }
-ND_KERNEL_SOURCES = ("csrc/nd.hip", "csrc/fqnm_device.h")
-ND_MEASURED_SOURCES_SHA = "b2a7aa91e2d37265"
+ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
+ND_MEASURED_SOURCES_SHA = "b7ce727f69fe384b"
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery
 TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
 
-# W6 (2-D Burgers, 4096 x 4096 int32): marching kernel, cells per lane, rows per wavefront
-ND_PLAN_W6 = (8, 12)
+# W6 (2-D Burgers, 4096 x 4096 int32): marching with temporal blocking --
+# kernel, cells per lane, steps per pass, rows per wavefront; and the
+# one-step-per-pass marching kernel (cells per lane, rows) timed beside it
+KERNEL_ND_MARCH, KERNEL_ND_TB = 6, 9
+ND_PLAN_W6 = (KERNEL_ND_TB, 2, 4, 24)
+ND_MARCH_PLAN_W6 = (8, 12)

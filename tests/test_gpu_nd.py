@@ -9,6 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2604_06947_amd import fqnm as F
+from paper_2604_06947_amd import plans
 from paper_2604_06947_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -43,8 +44,8 @@ def oracle_axes(axes):
 def gpu_nd(axes, q0, steps, plan=None):
     h = F.fqnm_create_nd(axes, q0)
     try:
-        if plan is not None:
-            F.fqnm_set_plan(h, F.KERNEL_ND_MARCH, plan[0], plan[1])
+        if plan is not None:  # (vec, rows) of the marching kernel, or (kernel, vec, depth)
+            F.fqnm_set_plan(h, *((F.KERNEL_ND_MARCH,) + tuple(plan) if len(plan) == 2 else plan))
         F.fqnm_step(h, steps)
         flat = F.fqnm_get_state(h, F.make_problem(axes[0].flux, axes[0].delta, axes[0].lambda_,
                                                   int(np.prod(q0.shape)), itype=axes[0].itype))
@@ -187,8 +188,16 @@ def test_nd_levels_and_autotune():
         F.fqnm_destroy(h)
 
 
-def test_nd_w6_full_size_sampled():
-    """W6 at its full 4096 x 4096 cells, 40 steps on the device; cells sampled
+W6_PLANS = {"default": None,
+            "benchmarked": (plans.ND_PLAN_W6[0], plans.ND_PLAN_W6[1],
+                            F.nd_tb_depth(plans.ND_PLAN_W6[2], plans.ND_PLAN_W6[3])),
+            "one_step": plans.ND_MARCH_PLAN_W6}
+
+
+@pytest.mark.parametrize("plan", list(W6_PLANS))
+def test_nd_w6_full_size_sampled(plan):
+    """W6 at its full 4096 x 4096 cells, 40 steps on the device (with the
+    default plan, the benchmarked one and one step per launch); cells sampled
     and checked against the oracle run on the (2s+1)^2 window around each (the
     5-point composition reaches s cells per direction in s steps)."""
     w = W.w6_burgers_2d()
@@ -197,7 +206,7 @@ def test_nd_w6_full_size_sampled():
     axes = axes_for(F.FLUX_BURGERS_EO, w.shape, F.I32, [F.BC_PERIODIC] * 2, list(w.lam),
                     delta=w.delta)
     s = 40
-    got, inv = gpu_nd(axes, q0, s)
+    got, inv = gpu_nd(axes, q0, s, W6_PLANS[plan])
     assert inv["sum"][0] == int(q0.sum())
     oax = [O.Problem(O.BURGERS_EO, w.delta, w.lam[m], bc=O.OUTFLOW, width=32) for m in range(2)]
     rng = np.random.default_rng(66)
@@ -209,3 +218,104 @@ def test_nd_w6_full_size_sampled():
         win = q0[np.ix_(jj, ii)]
         ref = O.step_nd(oax, win, s)
         assert got[j, i] == ref[s, s], (j, i)
+
+
+# ---------------------------------------------------------------------------
+# Temporal blocking on 2-D periodic int32 grids (kernel 9)
+# ---------------------------------------------------------------------------
+TB_PERIODIC = (F.BC_PERIODIC, F.BC_PERIODIC)
+
+
+def tb_case(flux, a_s, shape, seed, same=True):
+    q0, umax = field_q(shape, 1e-3, seed=seed)
+    a_s = a_s or [1.0, 1.0]
+    lams, alphas = lams_for(flux, umax, a_s, 2)
+    if not same:  # different constants per axis: the marching axis evaluates its own maps
+        lams = [lams[0], 0.8 * lams[1]]
+    return q0, axes_for(flux, shape, F.I32, TB_PERIODIC, lams, a_s, alphas)
+
+
+@pytest.mark.parametrize("flux,a_s", FLUXES)
+@pytest.mark.parametrize("same", [True, False])
+def test_nd_tb_matches_oracle(flux, a_s, same):
+    # 45 rows x 604 cells: several strips with a ragged last one at every
+    # (vec, depth), row blocks with a ragged tail; 13 steps = passes of 8, 4, 1
+    shape = (45, 604)
+    q0, axes = tb_case(flux, a_s, shape, seed=200 + flux, same=same)
+    steps = 13
+    ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
+    assert led == 0
+    for vec, K, rows in [(4, 4, 0), (4, 8, 16), (2, 2, 7), (2, 8, 3), (4, 1, 5), (2, 4, 64)]:
+        got, inv = gpu_nd(axes, q0, steps, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
+        assert np.array_equal(got, ref), (vec, K, rows)
+        assert inv["ledger"][0] == 0 and inv["sum"][0] == int(q0.sum())
+
+
+@pytest.mark.parametrize("shape", [(1, 4), (2, 8), (7, 4), (3, 260), (130, 12), (9, 1000),
+                                   (64, 256)])
+def test_nd_tb_small_and_ragged(shape):
+    # grids narrower than one strip (cells wrap inside a wavefront), fewer rows
+    # than the steps per pass, single rows
+    q0, axes = tb_case(F.FLUX_BURGERS_EO, None, shape, seed=shape[0] * 1000 + shape[1])
+    ref = O.step_nd(oracle_axes(axes), q0, 11)
+    for vec, K, rows in [(4, 8, 0), (2, 4, 1), (4, 2, 3), (2, 1, 2)]:
+        got, _ = gpu_nd(axes, q0, 11, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
+        assert np.array_equal(got, ref), (vec, K, rows)
+
+
+def test_nd_tb_refusals():
+    q0 = np.zeros((8, 8), dtype=np.int32)
+    ok = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, TB_PERIODIC, [0.3, 0.3])
+    bad = [axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, (F.BC_PERIODIC, F.BC_OUTFLOW), [0.3, 0.3]),
+           axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I64, TB_PERIODIC, [0.3, 0.3])]
+    for ax in bad:
+        h = F.fqnm_create_nd(ax, q0)
+        try:
+            with pytest.raises(F.FqnmError) as e:
+                F.fqnm_set_plan(h, F.KERNEL_ND_TB, 4, F.nd_tb_depth(4))
+            assert e.value.status == F.ERR_ARG
+        finally:
+            F.fqnm_destroy(h)
+    q3 = np.zeros((4, 4, 8), dtype=np.int32)
+    h = F.fqnm_create_nd(axes_for(F.FLUX_BURGERS_EO, q3.shape, F.I32, [F.BC_PERIODIC] * 3,
+                                  [0.2] * 3), q3)
+    try:
+        with pytest.raises(F.FqnmError):
+            F.fqnm_set_plan(h, F.KERNEL_ND_TB, 4, F.nd_tb_depth(4))
+    finally:
+        F.fqnm_destroy(h)
+    q6 = np.zeros((8, 6), dtype=np.int32)  # axis 0 of 6 cells: not a multiple of 4
+    h = F.fqnm_create_nd(axes_for(F.FLUX_BURGERS_EO, q6.shape, F.I32, TB_PERIODIC, [0.3, 0.3]), q6)
+    try:
+        with pytest.raises(F.FqnmError):
+            F.fqnm_set_plan(h, F.KERNEL_ND_TB, 4, F.nd_tb_depth(4))
+        F.fqnm_set_plan(h, F.KERNEL_ND_TB, 2, F.nd_tb_depth(4))  # 6 is a multiple of 2
+    finally:
+        F.fqnm_destroy(h)
+    h = F.fqnm_create_nd(ok, q0)
+    try:
+        for K in (3, 5, 16):
+            with pytest.raises(F.FqnmError):
+                F.fqnm_set_plan(h, F.KERNEL_ND_TB, 4, F.nd_tb_depth(K))
+    finally:
+        F.fqnm_destroy(h)
+
+
+def test_nd_tb_autotune_and_levels():
+    shape = (40, 520)
+    q0, axes = tb_case(F.FLUX_BURGERS_GODUNOV, None, shape, seed=91)
+    oax = oracle_axes(axes)
+    h = F.fqnm_create_nd(axes, q0)
+    try:
+        F.fqnm_autotune(h, 8)
+        assert F.fqnm_get_plan(h)["kernel"] in (F.KERNEL_ND_MARCH, F.KERNEL_ND_TB)
+        for kernel, vec, depth in [(F.KERNEL_ND_TB, 4, F.nd_tb_depth(8, 4)), (0, 0, 0)]:
+            if kernel:
+                F.fqnm_set_plan(h, kernel, vec, depth)
+            F.fqnm_step(h, 9)
+        ref = O.step_nd(oax, q0, 18)
+        flat = F.fqnm_get_state(h, F.make_problem(axes[0].flux, axes[0].delta, axes[0].lambda_,
+                                                  q0.size, itype=F.I32))
+        assert np.array_equal(flat.astype(np.int64).reshape(shape), ref)
+    finally:
+        F.fqnm_destroy(h)
