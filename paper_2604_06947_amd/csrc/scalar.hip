@@ -280,6 +280,19 @@ __device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, cons
   }
 }
 
+// Wavefront shifts by one lane that fill the end lane with 0 (lane l receives
+// lane l+1, or lane l-1).  Used where both end cells of the tile are halo, so
+// their values are never stored; the zero fill lets the compiler fold the
+// move into the add or subtract that consumes it.
+__device__ __forceinline__ uint32_t tb_from_next_z(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ uint32_t tb_from_prev_z(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x138, 0xf, 0xf, true));
+}
+
 // One step of a tile whose cells are held as their table addresses in the
 // wavefront's LDS slice: a = base + 8*(q - lo).  The update q - (F - F_left)
 // becomes a + 8*(F_left - F), so a step costs one clamp, one LDS read, one
@@ -296,11 +309,10 @@ __device__ __forceinline__ void tb_step_addr(uint32_t (&a)[V], uint32_t end) {
     pp[j] = static_cast<uint32_t>(e);
     pm[j] = static_cast<uint32_t>(e >> 32);
   }
-  const uint32_t pmn = lane_from_next<uint32_t>(pm[0]);
   uint32_t F[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) F[j] = pp[j] + (j + 1 < V ? pm[j + 1] : pmn);
-  const uint32_t Fl = lane_from_prev<uint32_t>(F[V - 1]);
+  for (int j = 0; j < V; ++j) F[j] = (j + 1 < V ? pm[j + 1] : tb_from_next_z(pm[0])) + pp[j];
+  const uint32_t Fl = tb_from_prev_z(F[V - 1]);
 #pragma unroll
   for (int j = 0; j < V; ++j) a[j] += ((j == 0 ? Fl : F[j - 1]) - F[j]) << 3;
 }

@@ -35,7 +35,9 @@ def test_fp64_div_sqrt_match_host():
                           torch.cuda.current_stream().cuda_stream)
     s, d = ds.cpu().numpy(), dd.cpu().numpy()
     assert np.array_equal(s.view(np.uint64), np.sqrt(a).view(np.uint64))
-    assert np.array_equal(d.view(np.uint64), (a / b).view(np.uint64))
+    with np.errstate(over="ignore"):  # exp(700) / 1e-3 overflows to inf on both sides
+        ref = a / b
+    assert np.array_equal(d.view(np.uint64), ref.view(np.uint64))
 
 
 def euler_case(n, kind, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), bc=F.BC_OUTFLOW):
