@@ -597,7 +597,7 @@ def main():
         extras["runtime_copy"] = runtime_copy_rate()
     # ---------------- CPU oracle baseline --------------------------------------------
     if not args.no_cpu:
-        csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "600"))
+        csteps = int(os.environ.get("FQNM_CPU_SAMPLE_STEPS", "2000"))  # about 12 s of one core
         log(f"[bench] cpu oracle sample: {w.n} cells x {csteps} steps")
         rate, dt = cpu_oracle_rate(w, csteps)
         model, avail = host_cpu()
