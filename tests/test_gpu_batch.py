@@ -111,6 +111,37 @@ def test_w4_sample_of_the_4096_instance_batch():
         assert int(got[i].sum()) == int(q0s[i].sum())
 
 
+def test_w4_full_batch_as_benchmarked():
+    """All 4096 instances of the seeded workload in one batch, as the
+    benchmark runs them: every instance equals the same instance advanced
+    alone by the single-grid stepper and conserves its sum (periodic), and a
+    seeded sample of 32 instances, drawn among those with at most 10^7
+    cell-updates, equals the oracle."""
+    ws = W.w4_batch()
+    probs = [F.make_problem(w.kind, w.delta, w.lam, w.n, itype=F.I32, a=w.a) for w in ws]
+    q0s = [O.quantise(w.u0, w.delta, 32) for w in ws]
+    steps = [w.steps for w in ws]
+    h = F.fqnm_batch_create(probs, [q.astype(np.int32) for q in q0s], steps)
+    try:
+        F.fqnm_batch_run(h)
+        got = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+        F.fqnm_batch_reset(h)
+        F.fqnm_batch_run_per_instance(h)
+        solo = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+    finally:
+        F.fqnm_batch_destroy(h)
+    for i in range(len(ws)):
+        assert np.array_equal(got[i], solo[i]), i
+        assert int(got[i].sum()) == int(q0s[i].sum()), i
+    small = [i for i, w in enumerate(ws) if w.n * w.steps <= 10 ** 7]
+    rng = np.random.default_rng(4096)
+    for i in rng.choice(small, size=32, replace=False):
+        w = ws[i]
+        op = O.Problem(O.UPWIND if w.kind == W.UPWIND else O.BURGERS_EO, w.delta, w.lam,
+                       width=32, a=w.a)
+        assert np.array_equal(got[i], O.step(op, q0s[i], steps[i])), i
+
+
 def test_batch_rejects_invalid_instances():
     p, q0, s, _ = instance(0, 100, 10, F.FLUX_UPWIND, F.BC_PERIODIC, seed=1)
     bad = F.make_problem(F.FLUX_UPWIND, 1e-4, 3.0, 100, itype=F.I32)  # CFL > 1

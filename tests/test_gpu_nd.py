@@ -319,3 +319,30 @@ def test_nd_tb_autotune_and_levels():
         assert np.array_equal(flat.astype(np.int64).reshape(shape), ref)
     finally:
         F.fqnm_destroy(h)
+
+
+def test_nd_tuned_plan_not_reused_across_boundary_kinds():
+    # a plan tuned (or set) on a periodic grid is cached for that grid's key;
+    # an outflow grid of the same extents and kind must not pick it up
+    shape = (24, 264)
+    q0, axes = tb_case(F.FLUX_BURGERS_EO, None, shape, seed=123)
+    h = F.fqnm_create_nd(axes, q0)
+    try:
+        assert F.fqnm_get_plan(h)["kernel"] == F.KERNEL_ND_TB  # the default of such grids
+        F.fqnm_autotune(h, 8)
+    finally:
+        F.fqnm_destroy(h)
+    out_axes = axes_for(F.FLUX_BURGERS_EO, shape, F.I32, (F.BC_OUTFLOW, F.BC_OUTFLOW),
+                        [a.lambda_ for a in axes])
+    ref, led = O.step_nd(oracle_axes(out_axes), q0, 9, return_ledger=True)
+    h = F.fqnm_create_nd(out_axes, q0)
+    try:
+        assert F.fqnm_get_plan(h)["kernel"] == F.KERNEL_ND_MARCH
+        F.fqnm_step(h, 9)
+        flat = F.fqnm_get_state(h, F.make_problem(F.FLUX_BURGERS_EO, axes[0].delta,
+                                                  axes[0].lambda_, q0.size, itype=F.I32))
+        inv = F.fqnm_invariants_get(h)
+    finally:
+        F.fqnm_destroy(h)
+    assert np.array_equal(flat.astype(np.int64).reshape(shape), ref)
+    assert inv["ledger"][0] == led
