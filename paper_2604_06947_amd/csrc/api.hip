@@ -548,7 +548,7 @@ fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0
   ctx->xp = ctx->nd.ax[0].x;
   ctx->pol = p0.flux == FQNM_FLUX_UPWIND ? P_UPWIND_POS : policy_of(p0, false);
   ctx->direct_pol = ctx->pol;
-  // 2-D int32 periodic grids default to 4 steps per pass, 2 cells per lane
+  // 2-D grids periodic on both axes default to 4 steps per pass, 2 cells per lane
   fqnm_plan pl{K_ND_MARCH, p0.itype == FQNM_I32 ? 4 : 2, 16, FQNM_EVAL_DIRECT};
   if (nd_tb_valid(p0.itype, ctx->pol, 2, ctx->nd)) pl = fqnm_plan{K_ND_TB, 2, 4, FQNM_EVAL_DIRECT};
   fqnm_plan cached;
@@ -821,13 +821,18 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
   if (ctx->dim > 1) {
     if (plan->kernel != 0 && plan->kernel != K_ND_MARCH && plan->kernel != K_ND_TB)
       return fail(FQNM_ERR_ARG, "d-D contexts run the marching kernels only");
-    if (plan->kernel) pl.kernel = plan->kernel;
+    if (plan->kernel && plan->kernel != pl.kernel) {
+      // a zero field of another kernel's plan takes that kernel's default
+      pl.kernel = plan->kernel;
+      pl.vec = pl.kernel == K_ND_TB ? 2 : (ctx->prob.itype == FQNM_I32 ? 4 : 2);
+      pl.depth = pl.kernel == K_ND_TB ? 4 : 16;
+    }
     if (plan->vec) pl.vec = plan->vec;
     if (plan->depth) pl.depth = plan->depth;
     if (pl.kernel == K_ND_TB) {
       if (!nd_tb_valid(ctx->prob.itype, ctx->pol, pl.vec, ctx->nd))
-        return fail(FQNM_ERR_ARG, "temporal blocking needs a 2-D int32 grid, periodic on both "
-                                  "axes, vec 2 or 4 dividing the first axis");
+        return fail(FQNM_ERR_ARG, "temporal blocking needs a 2-D grid periodic on both axes "
+                                  "and vec 2 or 4 (int64: 2) dividing the first axis");
       const int K = nd_tb_depth(pl);
       if (pl.depth < 1 || K < 1 || nd_tb_step_depth(K) != K)
         return fail(FQNM_ERR_ARG, "steps per pass (depth & 0xFF) must be 1, 2, 4 or 8");

@@ -37,19 +37,30 @@ __device__ __forceinline__ IT wadd(IT a, IT b) {
 
 // Wavefront shifts by one lane that fill the end lane with 0 (lane l receives
 // lane l+1, or lane l-1).  The ends belong to the strip's halo, whose values
-// are never stored; the zero fill lets the compiler fold the move into the
-// instruction that consumes it.
+// are never stored; the zero fill lets the compiler fold a 32-bit move into
+// the instruction that consumes it.  64-bit values move as two halves.
+template <int CTRL>
+__device__ __forceinline__ int tb_dpp0(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL, typename IT>
+__device__ __forceinline__ IT tb_shift(IT v) {
+  if constexpr (sizeof(IT) == 4) {
+    return __builtin_bit_cast(IT, tb_dpp0<CTRL>(__builtin_bit_cast(int, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(tb_dpp0<CTRL>(static_cast<int>(u)));
+    const uint32_t hi = static_cast<uint32_t>(tb_dpp0<CTRL>(static_cast<int>(u >> 32)));
+    return __builtin_bit_cast(IT, (static_cast<uint64_t>(hi) << 32) | lo);
+  }
+}
 template <typename IT>
 __device__ __forceinline__ IT tb_from_next(IT v) {
-  static_assert(sizeof(IT) == 4, "32-bit states");
-  return __builtin_bit_cast(IT, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf,
-                                                         0xf, true));
+  return tb_shift<0x130, IT>(v);
 }
 template <typename IT>
 __device__ __forceinline__ IT tb_from_prev(IT v) {
-  static_assert(sizeof(IT) == 4, "32-bit states");
-  return __builtin_bit_cast(IT, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf,
-                                                         0xf, true));
+  return tb_shift<0x138, IT>(v);
 }
 
 // One time level's registers (see the file comment).
@@ -225,17 +236,18 @@ hipError_t tb_by_k(int K, const void* src, void* dst, const NdParams& P, int row
 template <typename IT, int POL>
 hipError_t tb_by_vec(int vec, int K, const void* src, void* dst, const NdParams& P, int rows,
                      hipStream_t s) {
-  switch (vec) {
-    case 2: return tb_by_k<IT, POL, 2>(K, src, dst, P, rows, s);
-    case 4: return tb_by_k<IT, POL, 4>(K, src, dst, P, rows, s);
-    default: return hipErrorInvalidValue;
+  if (vec == 2) return tb_by_k<IT, POL, 2>(K, src, dst, P, rows, s);
+  if constexpr (sizeof(IT) == 4) {
+    if (vec == 4) return tb_by_k<IT, POL, 4>(K, src, dst, P, rows, s);
   }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 bool nd_tb_valid(int itype, int pol, int vec, const NdParams& P) {
-  if (itype != FQNM_I32 || (vec != 2 && vec != 4) || P.dim != 2) return false;
+  if (P.dim != 2) return false;
+  if (itype == FQNM_I32 ? (vec != 2 && vec != 4) : vec != 2) return false;
   if (P.ax[0].bc != FQNM_BC_PERIODIC || P.ax[1].bc != FQNM_BC_PERIODIC) return false;
   if (pol != P_UPWIND_POS && pol != P_EO && pol != P_GODUNOV && pol != P_MURMAN_ROE &&
       pol != P_LF_LINEAR && pol != P_LF_BURGERS)
@@ -249,19 +261,26 @@ int nd_tb_step_depth(int max_depth) {
   return 1;
 }
 
+template <typename IT>
+hipError_t tb_by_pol(int pol, int vec, int depth, const void* src, void* dst, const NdParams& P,
+                     int rows, hipStream_t s) {
+  switch (pol) {
+    case P_UPWIND_POS: return tb_by_vec<IT, P_UPWIND_POS>(vec, depth, src, dst, P, rows, s);
+    case P_EO: return tb_by_vec<IT, P_EO>(vec, depth, src, dst, P, rows, s);
+    case P_GODUNOV: return tb_by_vec<IT, P_GODUNOV>(vec, depth, src, dst, P, rows, s);
+    case P_MURMAN_ROE: return tb_by_vec<IT, P_MURMAN_ROE>(vec, depth, src, dst, P, rows, s);
+    case P_LF_LINEAR: return tb_by_vec<IT, P_LF_LINEAR>(vec, depth, src, dst, P, rows, s);
+    case P_LF_BURGERS: return tb_by_vec<IT, P_LF_BURGERS>(vec, depth, src, dst, P, rows, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_nd_tb(int itype, int pol, int vec, int depth, int rows, const void* src,
                         void* dst, const NdParams& P, hipStream_t s) {
   if (!nd_tb_valid(itype, pol, vec, P) || rows < 1 || nd_tb_step_depth(depth) != depth)
     return hipErrorInvalidValue;
-  switch (pol) {
-    case P_UPWIND_POS: return tb_by_vec<int32_t, P_UPWIND_POS>(vec, depth, src, dst, P, rows, s);
-    case P_EO: return tb_by_vec<int32_t, P_EO>(vec, depth, src, dst, P, rows, s);
-    case P_GODUNOV: return tb_by_vec<int32_t, P_GODUNOV>(vec, depth, src, dst, P, rows, s);
-    case P_MURMAN_ROE: return tb_by_vec<int32_t, P_MURMAN_ROE>(vec, depth, src, dst, P, rows, s);
-    case P_LF_LINEAR: return tb_by_vec<int32_t, P_LF_LINEAR>(vec, depth, src, dst, P, rows, s);
-    case P_LF_BURGERS: return tb_by_vec<int32_t, P_LF_BURGERS>(vec, depth, src, dst, P, rows, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (itype == FQNM_I32) return tb_by_pol<int32_t>(pol, vec, depth, src, dst, P, rows, s);
+  return tb_by_pol<int64_t>(pol, vec, depth, src, dst, P, rows, s);
 }
 
 }  // namespace fqnm

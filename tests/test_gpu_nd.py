@@ -226,26 +226,31 @@ def test_nd_w6_full_size_sampled(plan):
 TB_PERIODIC = (F.BC_PERIODIC, F.BC_PERIODIC)
 
 
-def tb_case(flux, a_s, shape, seed, same=True):
+def tb_case(flux, a_s, shape, seed, same=True, itype=F.I32):
     q0, umax = field_q(shape, 1e-3, seed=seed)
     a_s = a_s or [1.0, 1.0]
     lams, alphas = lams_for(flux, umax, a_s, 2)
     if not same:  # different constants per axis: the marching axis evaluates its own maps
         lams = [lams[0], 0.8 * lams[1]]
-    return q0, axes_for(flux, shape, F.I32, TB_PERIODIC, lams, a_s, alphas)
+    return q0, axes_for(flux, shape, itype, TB_PERIODIC, lams, a_s, alphas)
+
+
+TB_PLANS = {F.I32: [(4, 4, 0), (4, 8, 16), (2, 2, 7), (2, 8, 3), (4, 1, 5), (2, 4, 64)],
+            F.I64: [(2, 4, 0), (2, 8, 16), (2, 2, 7), (2, 1, 3)]}
 
 
 @pytest.mark.parametrize("flux,a_s", FLUXES)
 @pytest.mark.parametrize("same", [True, False])
-def test_nd_tb_matches_oracle(flux, a_s, same):
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+def test_nd_tb_matches_oracle(flux, a_s, same, itype):
     # 45 rows x 604 cells: several strips with a ragged last one at every
     # (vec, depth), row blocks with a ragged tail; 13 steps = passes of 8, 4, 1
     shape = (45, 604)
-    q0, axes = tb_case(flux, a_s, shape, seed=200 + flux, same=same)
+    q0, axes = tb_case(flux, a_s, shape, seed=200 + flux, same=same, itype=itype)
     steps = 13
     ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
     assert led == 0
-    for vec, K, rows in [(4, 4, 0), (4, 8, 16), (2, 2, 7), (2, 8, 3), (4, 1, 5), (2, 4, 64)]:
+    for vec, K, rows in TB_PLANS[itype]:
         got, inv = gpu_nd(axes, q0, steps, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
         assert np.array_equal(got, ref), (vec, K, rows)
         assert inv["ledger"][0] == 0 and inv["sum"][0] == int(q0.sum())
@@ -267,7 +272,7 @@ def test_nd_tb_refusals():
     q0 = np.zeros((8, 8), dtype=np.int32)
     ok = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, TB_PERIODIC, [0.3, 0.3])
     bad = [axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, (F.BC_PERIODIC, F.BC_OUTFLOW), [0.3, 0.3]),
-           axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I64, TB_PERIODIC, [0.3, 0.3])]
+           axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I64, TB_PERIODIC, [0.3, 0.3])]  # vec 4
     for ax in bad:
         h = F.fqnm_create_nd(ax, q0)
         try:
@@ -346,3 +351,23 @@ def test_nd_tuned_plan_not_reused_across_boundary_kinds():
         F.fqnm_destroy(h)
     assert np.array_equal(flat.astype(np.int64).reshape(shape), ref)
     assert inv["ledger"][0] == led
+
+
+def test_nd_plan_switch_takes_defaults():
+    q0, axes = tb_case(F.FLUX_BURGERS_EO, None, (16, 128), seed=5)
+    h = F.fqnm_create_nd(axes, q0)
+    try:
+        F.fqnm_set_plan(h, F.KERNEL_ND_TB, 4, F.nd_tb_depth(8, 24))
+        F.fqnm_set_plan(h, F.KERNEL_ND_MARCH)
+        pl = F.fqnm_get_plan(h)
+        assert (pl["kernel"], pl["vec"], pl["depth"]) == (F.KERNEL_ND_MARCH, 4, 16)
+        F.fqnm_set_plan(h, F.KERNEL_ND_TB)
+        pl = F.fqnm_get_plan(h)
+        assert (pl["kernel"], pl["vec"], pl["depth"]) == (F.KERNEL_ND_TB, 2, 4)
+        F.fqnm_step(h, 6)
+        flat = F.fqnm_get_state(h, F.make_problem(axes[0].flux, axes[0].delta, axes[0].lambda_,
+                                                  q0.size, itype=F.I32))
+    finally:
+        F.fqnm_destroy(h)
+    ref = O.step_nd(oracle_axes(axes), q0, 6)
+    assert np.array_equal(flat.astype(np.int64).reshape(q0.shape), ref)
