@@ -139,8 +139,8 @@ typedef struct {
  * whose windows (64*vec cells, vec 2 or 4) overlap by 16 cells and are
  * refreshed from their neighbours every 8 steps, `depth` <= 64*vec - 16 steps
  * per pass (int32 tables on periodic grids only); 9 = d-D marching with
- * temporal blocking (2-D grids periodic on both axes; vec 2 or 4 for int32, 2
- * for int64, dividing the length of axis 0): `depth & 0xFF` steps per pass (1, 2, 4 or 8; a
+ * temporal blocking (2-D grids; vec 2 or 4 for int32, 2 for int64, dividing
+ * the length of axis 0): `depth & 0xFF` steps per pass (1, 2, 4 or 8; a
  * remainder runs as smaller passes) and `depth >> 8` cells marched along
  * axis 1 per wavefront (0 = chosen from the grid size).  d-D contexts run
  * kernels 6 and 9 only.  Zero fields mean "keep" (on a change between

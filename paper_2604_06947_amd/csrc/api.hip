@@ -548,7 +548,7 @@ fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0
   ctx->xp = ctx->nd.ax[0].x;
   ctx->pol = p0.flux == FQNM_FLUX_UPWIND ? P_UPWIND_POS : policy_of(p0, false);
   ctx->direct_pol = ctx->pol;
-  // 2-D grids periodic on both axes default to 4 steps per pass, 2 cells per lane
+  // 2-D grids default to 4 steps per pass, 2 cells per lane
   fqnm_plan pl{K_ND_MARCH, p0.itype == FQNM_I32 ? 4 : 2, 16, FQNM_EVAL_DIRECT};
   if (nd_tb_valid(p0.itype, ctx->pol, 2, ctx->nd)) pl = fqnm_plan{K_ND_TB, 2, 4, FQNM_EVAL_DIRECT};
   fqnm_plan cached;
@@ -632,7 +632,7 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
     } else if (ctx->dim > 1 && pl.kernel == K_ND_TB) {
       k = nd_tb_step_depth(static_cast<int>(std::min<int64_t>(nd_tb_depth(pl), left)));
       e = launch_nd_tb(p.itype, ctx->pol, pl.vec, static_cast<int>(k), nd_tb_rows(ctx, pl), src,
-                       dst, ctx->nd, ctx->stream);
+                       dst, ctx->nd, ctx->d_ledger, ctx->stream);
     } else if (ctx->dim > 1) {
       e = launch_nd(p.itype, ctx->pol, pl.vec, pl.depth, src, dst, ctx->nd, ctx->d_ledger,
                     ctx->stream);
@@ -831,8 +831,8 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
     if (plan->depth) pl.depth = plan->depth;
     if (pl.kernel == K_ND_TB) {
       if (!nd_tb_valid(ctx->prob.itype, ctx->pol, pl.vec, ctx->nd))
-        return fail(FQNM_ERR_ARG, "temporal blocking needs a 2-D grid periodic on both axes "
-                                  "and vec 2 or 4 (int64: 2) dividing the first axis");
+        return fail(FQNM_ERR_ARG, "temporal blocking needs a 2-D grid and vec 2 or 4 (int64: 2) "
+                                  "dividing the first axis");
       const int K = nd_tb_depth(pl);
       if (pl.depth < 1 || K < 1 || nd_tb_step_depth(K) != K)
         return fail(FQNM_ERR_ARG, "steps per pass (depth & 0xFF) must be 1, 2, 4 or 8");

@@ -22,7 +22,7 @@ enum : int {
   K_ND_MARCH = 6,  // d-D grids: strips along axis 0 marching along the last axis
   K_TBLOCK_WG4 = 7,  // workgroup tiles of 4 or 8 wavefronts with overlapping windows
   K_TBLOCK_WG8 = 8,  // (int32 tables, periodic grids)
-  K_ND_TB = 9        // 2-D periodic grids: several steps per pass
+  K_ND_TB = 9        // 2-D grids: several steps per pass
 };
 
 // Per-block partial results of the reduction kernel (one record per block).
@@ -77,14 +77,14 @@ bool nd_variant_available(int itype, int pol, int vec);
 // UPWIND of either sign).
 hipError_t launch_nd(int itype, int pol, int vec, int rows, const void* src, void* dst,
                      const NdParams& P, long long* d_ledger, hipStream_t s);
-// Temporal blocking on 2-D periodic grids (K_ND_TB): `depth` steps of
+// Temporal blocking on 2-D grids (K_ND_TB): `depth` steps of
 // eq:nd_transfer_rule per launch, depth in {1, 2, 4, 8}; vec 2 or 4 (int64: 2)
 // and a first axis whose length is a multiple of vec.  nd_tb_step_depth gives the largest
 // available depth not above max_depth.
 bool nd_tb_valid(int itype, int pol, int vec, const NdParams& P);
 int nd_tb_step_depth(int max_depth);
 hipError_t launch_nd_tb(int itype, int pol, int vec, int depth, int rows, const void* src,
-                        void* dst, const NdParams& P, hipStream_t s);
+                        void* dst, const NdParams& P, long long* d_ledger, hipStream_t s);
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
                             int64_t count, hipStream_t s);

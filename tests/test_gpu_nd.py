@@ -226,13 +226,13 @@ def test_nd_w6_full_size_sampled(plan):
 TB_PERIODIC = (F.BC_PERIODIC, F.BC_PERIODIC)
 
 
-def tb_case(flux, a_s, shape, seed, same=True, itype=F.I32):
+def tb_case(flux, a_s, shape, seed, same=True, itype=F.I32, bcs=TB_PERIODIC):
     q0, umax = field_q(shape, 1e-3, seed=seed)
     a_s = a_s or [1.0, 1.0]
     lams, alphas = lams_for(flux, umax, a_s, 2)
     if not same:  # different constants per axis: the marching axis evaluates its own maps
         lams = [lams[0], 0.8 * lams[1]]
-    return q0, axes_for(flux, shape, itype, TB_PERIODIC, lams, a_s, alphas)
+    return q0, axes_for(flux, shape, itype, bcs, lams, a_s, alphas)
 
 
 TB_PLANS = {F.I32: [(4, 4, 0), (4, 8, 16), (2, 2, 7), (2, 8, 3), (4, 1, 5), (2, 4, 64)],
@@ -258,21 +258,41 @@ def test_nd_tb_matches_oracle(flux, a_s, same, itype):
 
 @pytest.mark.parametrize("shape", [(1, 4), (2, 8), (7, 4), (3, 260), (130, 12), (9, 1000),
                                    (64, 256)])
-def test_nd_tb_small_and_ragged(shape):
-    # grids narrower than one strip (cells wrap inside a wavefront), fewer rows
-    # than the steps per pass, single rows
-    q0, axes = tb_case(F.FLUX_BURGERS_EO, None, shape, seed=shape[0] * 1000 + shape[1])
-    ref = O.step_nd(oracle_axes(axes), q0, 11)
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+def test_nd_tb_small_and_ragged(shape, bc):
+    # grids narrower than one strip (cells wrap or clamp inside a wavefront),
+    # fewer rows than the steps per pass, single rows
+    q0, axes = tb_case(F.FLUX_BURGERS_EO, None, shape, seed=shape[0] * 1000 + shape[1],
+                       bcs=(bc, bc))
+    ref, led = O.step_nd(oracle_axes(axes), q0, 11, return_ledger=True)
     for vec, K, rows in [(4, 8, 0), (2, 4, 1), (4, 2, 3), (2, 1, 2)]:
-        got, _ = gpu_nd(axes, q0, 11, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
+        got, inv = gpu_nd(axes, q0, 11, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
         assert np.array_equal(got, ref), (vec, K, rows)
+        assert inv["ledger"][0] == led, (vec, K, rows)
+
+
+@pytest.mark.parametrize("flux,a_s", FLUXES)
+@pytest.mark.parametrize("bcs", [(F.BC_OUTFLOW, F.BC_OUTFLOW), (F.BC_OUTFLOW, F.BC_PERIODIC),
+                                 (F.BC_PERIODIC, F.BC_OUTFLOW)])
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+def test_nd_tb_outflow_matches_oracle(flux, a_s, bcs, itype):
+    # outflow ends on either axis: states and the boundary ledger, with strips
+    # and row blocks that end on the grid's edges and inside it
+    shape = (45, 604)
+    q0, axes = tb_case(flux, a_s, shape, seed=300 + flux, itype=itype, bcs=bcs)
+    steps = 13
+    ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
+    for vec, K, rows in TB_PLANS[itype]:
+        got, inv = gpu_nd(axes, q0, steps, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
+        assert np.array_equal(got, ref), (vec, K, rows)
+        assert inv["ledger"][0] == led, (vec, K, rows)
+        assert inv["sum"][0] == int(q0.sum()) + led
 
 
 def test_nd_tb_refusals():
     q0 = np.zeros((8, 8), dtype=np.int32)
     ok = axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, TB_PERIODIC, [0.3, 0.3])
-    bad = [axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I32, (F.BC_PERIODIC, F.BC_OUTFLOW), [0.3, 0.3]),
-           axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I64, TB_PERIODIC, [0.3, 0.3])]  # vec 4
+    bad = [axes_for(F.FLUX_BURGERS_EO, q0.shape, F.I64, TB_PERIODIC, [0.3, 0.3])]  # vec 4
     for ax in bad:
         h = F.fqnm_create_nd(ax, q0)
         try:
@@ -342,7 +362,7 @@ def test_nd_tuned_plan_not_reused_across_boundary_kinds():
     ref, led = O.step_nd(oracle_axes(out_axes), q0, 9, return_ledger=True)
     h = F.fqnm_create_nd(out_axes, q0)
     try:
-        assert F.fqnm_get_plan(h)["kernel"] == F.KERNEL_ND_MARCH
+        assert F.fqnm_get_plan(h)["kernel"] in (F.KERNEL_ND_MARCH, F.KERNEL_ND_TB)
         F.fqnm_step(h, 9)
         flat = F.fqnm_get_state(h, F.make_problem(F.FLUX_BURGERS_EO, axes[0].delta,
                                                   axes[0].lambda_, q0.size, itype=F.I32))
@@ -371,3 +391,22 @@ def test_nd_plan_switch_takes_defaults():
         F.fqnm_destroy(h)
     ref = O.step_nd(oracle_axes(axes), q0, 6)
     assert np.array_equal(flat.astype(np.int64).reshape(q0.shape), ref)
+
+
+@pytest.mark.parametrize("flux", [F.FLUX_BURGERS_EO, F.FLUX_BURGERS_GODUNOV])
+@pytest.mark.parametrize("bcs", [(F.BC_OUTFLOW, F.BC_OUTFLOW), (F.BC_OUTFLOW, F.BC_PERIODIC),
+                                 (F.BC_PERIODIC, F.BC_OUTFLOW)])
+@pytest.mark.parametrize("itype", [F.I32, F.I64])
+def test_nd_tb_halo_past_an_outflow_end(flux, bcs, itype):
+    # 602 cells along axis 0: with 2 cells per lane and 4 steps per pass the
+    # strip storing cells 480..599 loads cells up to 603, past the end, though
+    # none of its stored cells is an end cell; with 12 rows per wavefront the
+    # block storing rows 24..35 loads rows past the last row (36) likewise
+    shape = (37, 602)
+    q0, axes = tb_case(flux, None, shape, seed=602 + flux, itype=itype, bcs=bcs)
+    steps = 15
+    ref, led = O.step_nd(oracle_axes(axes), q0, steps, return_ledger=True)
+    for vec, K, rows in [(2, 4, 12), (2, 8, 16), (2, 2, 5), (2, 1, 7)]:
+        got, inv = gpu_nd(axes, q0, steps, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
+        assert np.array_equal(got, ref), (vec, K, rows)
+        assert inv["ledger"][0] == led, (vec, K, rows)
