@@ -311,7 +311,7 @@ def bench_nd(F, W, plans, stream, reps=3):
     return {"w6_burgers_2d": {
         "cells": cells, "shape": [ny, nx], "time_steps": w.steps, "cell_updates_per_s": rate,
         "ms_per_solve": t * 1e3, "plan": {"vec": vec, "steps_per_launch": K, "rows": rows},
-        "kernel": "k_nd_tb<int, P_EO, %d, %d, true>" % (vec, K),
+        "kernel": "k_nd_tb<int, P_EO, %d, %d, true, false>" % (vec, K),
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "bytes_per_cell_update": 8,
                      "traffic": plans.TRAFFIC_BYTES_PER_LAUNCH["w6"] if measured else None,
