@@ -135,12 +135,13 @@ __device__ __forceinline__ void tb_row(const NdParams& P, const TbEdges& E, cons
 // alternate between two register sets, so nothing is copied.
 //
 // OUT: m is the incoming row's index, [j0, jend) the rows this wavefront
-// owns, ftop the level's kept transfer above the last row, led the ledger.
+// owns, ynear whether this iteration's rows reach row 0 or the last row, ftop
+// the level's kept transfer above the last row, led the ledger.
 template <typename IT, int POL, int V, bool SAME, bool OUT>
 __device__ __forceinline__ void tb_feed(const NdParams& P, const TbEdges& E,
                                         const TbLevel<IT, V>& X, TbLevel<IT, V>& Y,
                                         const IT (&in)[V], IT (&out)[V], int64_t m, int64_t j0,
-                                        int64_t jend, IT (&ftop)[V], long long& led) {
+                                        int64_t jend, bool ynear, IT (&ftop)[V], long long& led) {
   IT Fx[V], Fl, pp[V], pm[V];
   tb_row<IT, POL, V, SAME, OUT>(P, E, in, Fx, Fl, pp, pm);
   const int64_t ny = P.ax[1].n;
@@ -157,7 +158,7 @@ __device__ __forceinline__ void tb_feed(const NdParams& P, const TbEdges& E,
     if constexpr (NdSplit<POL>::value) f = wadd<IT>(X.aux[k], pm[k]);
     else f = transfer<IT, POL>(P.ax[1].x, X.aux[k], in[k]);
     if constexpr (OUT) {
-      if (E.oy) {  // uniform, as are the row tests
+      if (E.oy && ynear) {  // uniform, as are the row tests
         if (m == 0 || m == ny - 1) {
           IT self;
           if constexpr (NdSplit<POL>::value) self = wadd<IT>(pp[k], pm[k]);
@@ -248,11 +249,14 @@ __device__ __forceinline__ void tb_march(const IT* __restrict__ src, IT* __restr
     // level s + 1 receives exact rows from iteration 2s on (what it held
     // before then flushes out of its registers); its incoming row is
     // j0 - K + p - s
+    const int64_t sb = j0 - K + p;
+    const bool ynear = EDGES && oy && ((sb - (K - 1) <= 0 && sb >= 0) ||
+                                       (sb - (K - 1) <= ny && sb >= ny - 1));
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       if (p < 2 * s) break;  // uniform
       IT out[V];
-      tb_feed<IT, POL, V, SAME, EDGES>(P, E, X[s], Y[s], cur, out, j0 - K + p - s, j0, jend,
+      tb_feed<IT, POL, V, SAME, EDGES>(P, E, X[s], Y[s], cur, out, sb - s, j0, jend, ynear,
                                        ftop[s], led);
 #pragma unroll
       for (int k = 0; k < V; ++k) cur[k] = out[k];
@@ -273,12 +277,23 @@ __device__ __forceinline__ void tb_march(const IT* __restrict__ src, IT* __restr
   }
 }
 
+// Wavefronts to (strip, row block).  The ni interior strips [first, first + ni)
+// come first, `rows` rows per wavefront; then the ne strips whose loaded range
+// reaches past an end of an outflow axis 0 (strip 0 and strips te and above),
+// rows_e rows per wavefront: they run the slower boundary code, and shorter
+// marches keep them from setting the launch's length.  Without outflow along
+// axis 0 every strip is interior.
+struct TbMap {
+  int64_t ni, first, te, ne, nblk, nblk_e;
+  int32_t rows, rows_e;
+};
+
 // SAME: both axes have the same map constants, so axis 1 reuses axis 0's maps.
 // OUT: at least one axis is outflow.
 template <typename IT, int POL, int V, int K, bool SAME, bool OUT>
 __global__ __launch_bounds__(256) void k_nd_tb(const IT* __restrict__ src, IT* __restrict__ dst,
-                                               NdParams P, int rows, int64_t nstrips,
-                                               int64_t nwaves, long long* __restrict__ ledger) {
+                                               NdParams P, TbMap M, int64_t nwaves,
+                                               long long* __restrict__ ledger) {
   constexpr int H = tb_halo<V>(K);
   constexpr int W = 64 * V - 2 * H;  // cells stored per strip
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -286,9 +301,20 @@ __global__ __launch_bounds__(256) void k_nd_tb(const IT* __restrict__ src, IT* _
   const int64_t w = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
   if (w >= nwaves) return;
   const int64_t nx = P.ax[0].n, ny = P.ax[1].n;
-  const int64_t xs = (w % nstrips) * W;  // first stored cell of the strip
-  const int64_t j0 = (w / nstrips) * rows;
-  const int64_t jend = j0 + rows < ny ? j0 + rows : ny;
+  int64_t strip, j0, rws;
+  if (w < M.ni * M.nblk) {
+    strip = M.first + w % M.ni;
+    j0 = (w / M.ni) * M.rows;
+    rws = M.rows;
+  } else {
+    const int64_t w2 = w - M.ni * M.nblk;
+    const int64_t e = w2 % M.ne;
+    strip = (M.first == 1 && e == 0) ? 0 : M.te + e - M.first;
+    j0 = (w2 / M.ne) * M.rows_e;
+    rws = M.rows_e;
+  }
+  const int64_t xs = strip * W;  // first stored cell of the strip
+  const int64_t jend = j0 + rws < ny ? j0 + rws : ny;
   if constexpr (OUT) {
     const bool edges =
         (P.ax[0].bc == FQNM_BC_OUTFLOW && (xs - H < 0 || xs - H + 64 * V > nx)) ||
@@ -302,21 +328,41 @@ __global__ __launch_bounds__(256) void k_nd_tb(const IT* __restrict__ src, IT* _
 }
 
 template <typename IT, int POL, int V, int K, bool SAME>
-void tb_go(dim3 g, const IT* a, IT* d, const NdParams& P, int rows, int64_t nstrips,
-           int64_t nwaves, long long* led, hipStream_t s) {
+void tb_go(dim3 g, const IT* a, IT* d, const NdParams& P, const TbMap& M, int64_t nwaves,
+           long long* led, hipStream_t s) {
   if (P.ax[0].bc == FQNM_BC_OUTFLOW || P.ax[1].bc == FQNM_BC_OUTFLOW)
-    k_nd_tb<IT, POL, V, K, SAME, true><<<g, dim3(256), 0, s>>>(a, d, P, rows, nstrips, nwaves, led);
+    k_nd_tb<IT, POL, V, K, SAME, true><<<g, dim3(256), 0, s>>>(a, d, P, M, nwaves, led);
   else
-    k_nd_tb<IT, POL, V, K, SAME, false><<<g, dim3(256), 0, s>>>(a, d, P, rows, nstrips, nwaves,
-                                                                 led);
+    k_nd_tb<IT, POL, V, K, SAME, false><<<g, dim3(256), 0, s>>>(a, d, P, M, nwaves, led);
 }
 
 template <typename IT, int POL, int V, int K>
 hipError_t tb_launch(const void* src, void* dst, const NdParams& P, int rows, long long* led,
                      hipStream_t s) {
-  constexpr int W = 64 * V - 2 * tb_halo<V>(K);
-  const int64_t nstrips = (P.ax[0].n + W - 1) / W;
-  const int64_t nwaves = nstrips * ((P.ax[1].n + rows - 1) / rows);
+  constexpr int H = tb_halo<V>(K);
+  constexpr int W = 64 * V - 2 * H;
+  const int64_t nx = P.ax[0].n, ny = P.ax[1].n;
+  const int64_t nstrips = (nx + W - 1) / W;
+  TbMap M;
+  M.rows = rows;
+  M.rows_e = rows > 1 ? rows / 2 : 1;
+  M.nblk = (ny + rows - 1) / rows;
+  M.nblk_e = (ny + M.rows_e - 1) / M.rows_e;
+  if (P.ax[0].bc == FQNM_BC_OUTFLOW) {
+    // strip t loads cells [tW - H, tW - H + 64V): strip 0 and the strips with
+    // tW + W + H > nx reach past an end
+    M.first = 1;
+    const int64_t last_in = nx - W - H >= 0 ? (nx - W - H) / W : 0;  // last t inside
+    M.te = last_in + 1 > nstrips ? nstrips : (last_in + 1 < 1 ? 1 : last_in + 1);
+    M.ni = M.te - 1;
+    M.ne = nstrips - M.ni;
+  } else {
+    M.first = 0;
+    M.te = nstrips;
+    M.ni = nstrips;
+    M.ne = 0;
+  }
+  const int64_t nwaves = M.ni * M.nblk + M.ne * M.nblk_e;
   const int64_t blocks = (nwaves + 3) / 4;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
   const dim3 g(static_cast<unsigned>(blocks));
@@ -327,11 +373,11 @@ hipError_t tb_launch(const void* src, void* dst, const NdParams& P, int rows, lo
                     X.x.alpha == Y.x.alpha && X.x.delta == Y.x.delta && X.x.lambda == Y.x.lambda;
   if constexpr (NdSplit<POL>::value) {
     if (same) {
-      tb_go<IT, POL, V, K, true>(g, a, d, P, rows, nstrips, nwaves, led, s);
+      tb_go<IT, POL, V, K, true>(g, a, d, P, M, nwaves, led, s);
       return hipGetLastError();
     }
   }
-  tb_go<IT, POL, V, K, false>(g, a, d, P, rows, nstrips, nwaves, led, s);
+  tb_go<IT, POL, V, K, false>(g, a, d, P, M, nwaves, led, s);
   return hipGetLastError();
 }
 
