@@ -18,10 +18,10 @@ KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
 MEASURED_SOURCES_SHA = "1bf916568d283281"
 TRAFFIC_BYTES_PER_LAUNCH = {
     "w2": 11502 * 1024,  # k_tblock<int, P_LUT, 4>, 48 steps per launch
-    "w6": 153379 * 1024,  # k_nd_tb<int, P_EO, 2, 4, true>, 24 rows per wavefront, 4 steps
+    "w6": 153373 * 1024,  # k_nd_tb<int, P_EO, 2, 4, true>, 24 rows per wavefront, 4 steps
 }
 ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
-ND_MEASURED_SOURCES_SHA = "91c7df3e7fef13a9"
+ND_MEASURED_SOURCES_SHA = "7b152cdb582ada5a"
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery
 TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
