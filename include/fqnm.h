@@ -241,7 +241,10 @@ fqnm_status fqnm_create_classical(const fqnm_problem* prob, const double* u0_hos
  * i_0 + n_0*(i_1 + n_1*i_2) of q0_host (prod n_m values of itype, copied).
  * Outflow ends copy the cell into its ghost, per direction.  The single-grid
  * calls (step, get/state, reconstruct, invariants, plans, autotune, level
- * statistics, destroy) apply with n = prod n_m.  Errors: FQNM_ERR_ARG for a
+ * statistics, destroy) apply with n = prod n_m.  2-D grids start on the
+ * temporally blocked marching kernel (plan kernel 9: 2 cells per lane, 4
+ * steps per launch), or on kernel 6 when n_0 is odd; 3-D grids start on the
+ * one-step marching kernel (kernel 6).  Errors: FQNM_ERR_ARG for a
  * bad dim, an invalid axis, axes that disagree, more than 2^36 cells, or
  * an axis of 2^31 cells or more;
  * FQNM_ERR_UNSUPPORTED for Euler kinds and for eval = FQNM_EVAL_LUT (the
