@@ -410,3 +410,17 @@ def test_nd_tb_halo_past_an_outflow_end(flux, bcs, itype):
         got, inv = gpu_nd(axes, q0, steps, (F.KERNEL_ND_TB, vec, F.nd_tb_depth(K, rows)))
         assert np.array_equal(got, ref), (vec, K, rows)
         assert inv["ledger"][0] == led, (vec, K, rows)
+
+
+def test_nd_default_plans():
+    # 2-D grids start on the temporally blocked kernel, or on the one-step
+    # kernel when axis 0 has an odd length; both give the oracle's integers
+    for shape, kernel in [((20, 64), F.KERNEL_ND_TB), ((20, 37), F.KERNEL_ND_MARCH)]:
+        q0, axes = tb_case(F.FLUX_BURGERS_EO, None, shape, seed=shape[1])
+        h = F.fqnm_create_nd(axes, q0)
+        try:
+            assert F.fqnm_get_plan(h)["kernel"] == kernel, shape
+        finally:
+            F.fqnm_destroy(h)
+        got, _ = gpu_nd(axes, q0, 10)
+        assert np.array_equal(got, O.step_nd(oracle_axes(axes), q0, 10)), shape
