@@ -637,8 +637,9 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
       e = launch_nd(p.itype, ctx->pol, pl.vec, pl.depth, src, dst, ctx->nd, ctx->d_ledger,
                     ctx->stream);
     } else if (ctx->euler) {
+      k = std::min<int64_t>(euler_steps_per_launch(), left);
       e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
-                            p.bc, ctx->eparams, ctx->d_ledger, ctx->stream);
+                            p.bc, ctx->eparams, static_cast<int>(k), ctx->d_ledger, ctx->stream);
     } else if (pl.kernel == K_TBLOCK_WG4 || pl.kernel == K_TBLOCK_WG8) {
       k = std::min<int64_t>(pl.depth, left);
       e = launch_tblock_wg(pl.kernel == K_TBLOCK_WG4 ? 4 : 8, pl.vec,
@@ -810,7 +811,7 @@ fqnm_status fqnm_quantise(const double* u_host, int64_t n, double delta, int32_t
 fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out) {
   if (!ctx || !out) return fail(FQNM_ERR_ARG, "NULL argument");
   *out = ctx->plan;
-  if (ctx->euler) { out->kernel = K_STREAM; out->vec = 1; out->depth = 1; }
+  if (ctx->euler) { out->kernel = K_STREAM; out->vec = 1; out->depth = euler_steps_per_launch(); }
   return FQNM_OK;
 }
 

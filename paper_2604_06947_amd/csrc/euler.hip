@@ -16,11 +16,14 @@
 // delta); m and E take the classical update U - lambda*(F_R - F_L).
 //
 // Layout: three 8-byte arrays of n cells (rho, m, E) back to back, ping-pong.
-// A 256-thread block loads cells [b0-1, b0+255), computes the per-cell
-// primitives once into LDS, evaluates the 255 interfaces between them, and
-// updates the 254 cells [b0, b0+254).  Cells outside [0, n) are ghost copies
-// (periodic wrap or outflow copy of the end cell), so the outflow boundary
-// flux is F(U_0, U_0) = f(U_0).  Arithmetic per cell-update: one set of
+// A 256-thread block loads positions [b0-8, b0+248) and advances them up to 8
+// steps per launch: each step computes the per-cell primitives once into LDS,
+// evaluates the 255 interfaces between them and updates the 254 positions
+// that have both neighbours.  After step s the positions [s, 255-s] are exact,
+// so the 240 cells [b0, b0+240) are stored after up to 8 steps.  Positions
+// outside [0, n) are ghost copies (periodic wrap, or the outflow copy of the
+// end cell, renewed after every step), so the outflow boundary flux is
+// F(U_0, U_0) = f(U_0).  Arithmetic per cell-update: one set of
 // primitives (1 division, 1-2 square roots) and one Roe interface
 // (4 divisions, 1 square root, ~60 other FP64 operations); HBM traffic
 // 48 bytes (3 int64 read + 3 written).
@@ -32,8 +35,9 @@ namespace fqnm {
 
 namespace {
 
-constexpr int EB = 256;        // threads per block
-constexpr int ECELLS = EB - 2; // cells updated per block
+constexpr int EB = 256;               // threads per block
+constexpr int EKS = 8;                // steps per launch at most
+constexpr int ECELLS = EB - 2 * EKS;  // cells stored per block
 
 struct Prim {
   double r, u, p, H, s, c, f0, f1, f2;
@@ -183,92 +187,136 @@ __device__ __forceinline__ int64_t ghost(int64_t g, int64_t n, int bc) {
   return bc == FQNM_BC_PERIODIC ? wrap_index(g, n) : clamp_index(g, n);
 }
 
-// One step of one tile of cells [b0, b0 + ECELLS) of an n-cell problem.
+// Up to EKS steps (nst) of one tile of cells [b0, b0 + ECELLS) of an n-cell
+// problem; the block holds positions [b0 - EKS, b0 - EKS + EB).
 __device__ __forceinline__ void euler_tile_step(const int64_t* __restrict__ src,
                                                 int64_t* __restrict__ dst, int64_t n, int bc,
-                                                const EulerParams& E, int64_t b0,
+                                                const EulerParams& E, int64_t b0, int nst,
                                                 long long* __restrict__ ledger, Prim* s_prim,
-                                                int64_t (*s_T)[EB]) {
+                                                int64_t (*s_T)[EB], int64_t* s_edge) {
   const int t = threadIdx.x;
-  const int64_t g = b0 - 1 + t;  // cell of this thread
+  const int64_t g = b0 - EKS + t;  // cell of this thread
   const int64_t gi = ghost(g, n, bc);
-  const int64_t qr = src[gi], qm = src[n + gi], qE = src[2 * n + gi];
-  s_prim[t] = cell_primitives(E, qr, qm, qE);
-  __syncthreads();
-  // interface between cells g and g+1 (thread t < EB-1)
-  int64_t T[3] = {0, 0, 0};
-  if (t < EB - 1) roe_transfer(E, s_prim[t], s_prim[t + 1], T);
-  s_T[0][t] = T[0];
-  s_T[1][t] = T[1];
-  s_T[2][t] = T[2];
-  __syncthreads();
-  if (t >= 1 && t <= ECELLS && g < n) {
-    dst[g] = qr - (T[0] - s_T[0][t - 1]);
-    if (E.dens) {
-      // classical update of the real-valued components
-      const double dm = __builtin_bit_cast(double, T[1]) - __builtin_bit_cast(double, s_T[1][t - 1]);
-      const double dE = __builtin_bit_cast(double, T[2]) - __builtin_bit_cast(double, s_T[2][t - 1]);
-      const double tm = E.lambda * dm;
-      const double tE = E.lambda * dE;
-      dst[n + g] = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qm) - tm);
-      dst[2 * n + g] = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qE) - tE);
-    } else {
-      dst[n + g] = qm - (T[1] - s_T[1][t - 1]);
-      dst[2 * n + g] = qE - (T[2] - s_T[2][t - 1]);
+  int64_t qr = src[gi], qm = src[n + gi], qE = src[2 * n + gi];
+  const bool outflow = bc == FQNM_BC_OUTFLOW;
+  const bool stored = t >= EKS && t < EB - EKS && g < n;
+  // the block holds outflow ghosts, to be renewed after every step (uniform)
+  const bool ghosts = outflow && (b0 - EKS < 0 || b0 - EKS + EB > n);
+  const int nled = E.dens ? 1 : 3;  // density-only: only the counts have a ledger
+  for (int s = 0; s < nst; ++s) {
+    s_prim[t] = cell_primitives(E, qr, qm, qE);
+    __syncthreads();
+    // interface between positions t and t+1 (t < EB-1)
+    int64_t T[3] = {0, 0, 0};
+    if (t < EB - 1) roe_transfer(E, s_prim[t], s_prim[t + 1], T);
+    s_T[0][t] = T[0];
+    s_T[1][t] = T[1];
+    s_T[2][t] = T[2];
+    __syncthreads();
+    if (t >= 1 && t <= EB - 2) {  // positions with both neighbours
+      const int64_t Tl[3] = {s_T[0][t - 1], s_T[1][t - 1], s_T[2][t - 1]};
+      qr = qr - (T[0] - Tl[0]);
+      if (E.dens) {
+        // classical update of the real-valued components
+        const double dm = __builtin_bit_cast(double, T[1]) - __builtin_bit_cast(double, Tl[1]);
+        const double dE = __builtin_bit_cast(double, T[2]) - __builtin_bit_cast(double, Tl[2]);
+        const double tm = E.lambda * dm;
+        const double tE = E.lambda * dE;
+        qm = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qm) - tm);
+        qE = __builtin_bit_cast(int64_t, __builtin_bit_cast(double, qE) - tE);
+      } else {
+        qm = qm - (T[1] - Tl[1]);
+        qE = qE - (T[2] - Tl[2]);
+      }
+      if (outflow && stored) {
+        if (g == 0) {
+          for (int c = 0; c < nled; ++c)
+            atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
+                      static_cast<unsigned long long>(Tl[c]));
+        }
+        if (g == n - 1) {
+          for (int c = 0; c < nled; ++c)
+            atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
+                      static_cast<unsigned long long>(-static_cast<long long>(T[c])));
+        }
+      }
     }
-    const int nled = E.dens ? 1 : 3;  // density-only: only the counts have a ledger
-    if (bc == FQNM_BC_OUTFLOW) {
+    if (ghosts && s + 1 < nst) {  // uniform: the ghosts take the end cells' new states
       if (g == 0) {
-        for (int c = 0; c < nled; ++c)
-          atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
-                    static_cast<unsigned long long>(s_T[c][t - 1]));
+        s_edge[0] = qr;
+        s_edge[1] = qm;
+        s_edge[2] = qE;
       }
       if (g == n - 1) {
-        for (int c = 0; c < nled; ++c)
-          atomicAdd(reinterpret_cast<unsigned long long*>(ledger + c),
-                    static_cast<unsigned long long>(-static_cast<long long>(T[c])));
+        s_edge[3] = qr;
+        s_edge[4] = qm;
+        s_edge[5] = qE;
+      }
+      __syncthreads();
+      if (g < 0) {
+        qr = s_edge[0];
+        qm = s_edge[1];
+        qE = s_edge[2];
+      }
+      if (g >= n) {
+        qr = s_edge[3];
+        qm = s_edge[4];
+        qE = s_edge[5];
       }
     }
+  }
+  if (stored) {
+    dst[g] = qr;
+    dst[n + g] = qm;
+    dst[2 * n + g] = qE;
   }
 }
 
 __global__ __launch_bounds__(EB) void k_euler_step(const int64_t* __restrict__ src,
                                                    int64_t* __restrict__ dst, int64_t n, int bc,
-                                                   EulerParams E, long long* __restrict__ ledger) {
+                                                   EulerParams E, int nst,
+                                                   long long* __restrict__ ledger) {
   __shared__ Prim s_prim[EB];
   __shared__ int64_t s_T[3][EB];
+  __shared__ int64_t s_edge[6];
   const int64_t b0 = xcd_tile(blockIdx.x, gridDim.x) * ECELLS;
-  euler_tile_step(src, dst, n, bc, E, b0, ledger, s_prim, s_T);
+  euler_tile_step(src, dst, n, bc, E, b0, nst, ledger, s_prim, s_T, s_edge);
 }
 
 // Many independent problems in one launch: block b advances tile tiles[b] of
-// request tiles[b].req by one step, if that request still has a step to take
-// at this position `s` of the current tick.  Each request has its own
-// ping-pong buffers; its source buffer is given by (parity + s) & 1.
+// request tiles[b].req by up to EKS steps, if that request still has steps to
+// take from this position `s` (a multiple of EKS) of the current tick.  Each
+// request has its own ping-pong buffers; every launch writes the other one, so
+// its source buffer is given by (parity + s / EKS) & 1.
 __global__ __launch_bounds__(EB) void k_euler_multi(const EulerTile* __restrict__ tiles,
                                                     const EulerReq* __restrict__ reqs, int s) {
   __shared__ Prim s_prim[EB];
   __shared__ int64_t s_T[3][EB];
+  __shared__ int64_t s_edge[6];
   const EulerTile tl = tiles[blockIdx.x];
   const EulerReq& R = reqs[tl.req];
   if (s >= R.steps) return;  // uniform over the block
-  const int par = (R.parity + s) & 1;
+  const int nst = R.steps - s < EKS ? R.steps - s : EKS;
+  const int par = (R.parity + s / EKS) & 1;
   const int64_t* src = par ? R.buf1 : R.buf0;
   int64_t* dst = par ? R.buf0 : R.buf1;
-  euler_tile_step(src, dst, R.n, R.bc, R.E, tl.start, R.ledger, s_prim, s_T);
+  euler_tile_step(src, dst, R.n, R.bc, R.E, tl.start, nst, R.ledger, s_prim, s_T, s_edge);
 }
 
 }  // namespace
 
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
-                             const EulerParams& E, long long* d_ledger, hipStream_t s) {
+                             const EulerParams& E, int nsteps, long long* d_ledger, hipStream_t s) {
+  if (nsteps < 1 || nsteps > EKS) return hipErrorInvalidValue;
   const int64_t blocks = (n + ECELLS - 1) / ECELLS;
-  k_euler_step<<<dim3((unsigned)blocks), dim3(EB), 0, s>>>(src, dst, n, bc, E, d_ledger);
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  k_euler_step<<<dim3((unsigned)blocks), dim3(EB), 0, s>>>(src, dst, n, bc, E, nsteps, d_ledger);
   return hipGetLastError();
 }
 
 int64_t euler_tiles(int64_t n) { return (n + ECELLS - 1) / ECELLS; }
 int64_t euler_tile_cells() { return ECELLS; }
+int euler_steps_per_launch() { return EKS; }
 
 hipError_t launch_euler_multi(const EulerTile* d_tiles, int64_t ntiles, const EulerReq* d_reqs,
                               int s, hipStream_t st) {

@@ -105,8 +105,10 @@ struct EulerParams {
   int fix;    // entropy fix on the acoustic waves
   int dens;   // density-only: components 1, 2 hold FP64 m and E (bit patterns)
 };
+// nsteps (1 .. euler_steps_per_launch()) steps in one launch.
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,
-                             const EulerParams& E, long long* d_ledger, hipStream_t s);
+                             const EulerParams& E, int nsteps, long long* d_ledger, hipStream_t s);
+int euler_steps_per_launch();
 
 // Many Euler problems advanced together, one step per launch.
 struct EulerReq {
@@ -127,6 +129,8 @@ struct EulerTile {
 };
 int64_t euler_tiles(int64_t n);
 int64_t euler_tile_cells();
+// Steps s .. s + euler_steps_per_launch() - 1 of the current tick (s a
+// multiple of euler_steps_per_launch()), for every request that has them.
 hipError_t launch_euler_multi(const EulerTile* d_tiles, int64_t ntiles, const EulerReq* d_reqs,
                               int s, hipStream_t st);
 

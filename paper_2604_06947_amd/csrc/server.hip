@@ -7,8 +7,9 @@
 //   2. advances every admitted request by up to `tick_steps` steps:
 //        - int32 scalar requests that fit a workgroup: one launch of the
 //          register-resident batch kernel for all of them;
-//        - Euler requests: `tick_steps` launches of the multi-request step
-//          kernel, each covering the tiles of every Euler request;
+//        - Euler requests: launches of the multi-request step kernel, each
+//          covering the tiles of every Euler request and advancing them up
+//          to 8 steps;
 //        - other scalar requests: their single-grid stepper;
 //   3. copies finished states to the caller's buffers, stamps completion
 //      times and frees their arena blocks.
@@ -319,7 +320,8 @@ bool run_tick(fqnm_server* s) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->d_etile, et.data(), sizeof(EulerTile) * et.size(),
                          hipMemcpyHostToDevice, s->stream);
-    for (int k = 0; k < emax && e == hipSuccess; ++k)
+    const int ks = euler_steps_per_launch();
+    for (int k = 0; k < emax && e == hipSuccess; k += ks)
       e = launch_euler_multi(s->d_etile, static_cast<int64_t>(et.size()), s->d_ereq, k, s->stream);
   }
   for (SReq* r : singles) {
@@ -335,7 +337,10 @@ bool run_tick(fqnm_server* s) {
   for (SReq* r : s->active) {
     if (r->status != FQNM_OK || r->tick_steps <= 0) continue;
     r->done += r->tick_steps;
-    if (r->path == R_EULER) r->parity = static_cast<int>((r->parity + r->tick_steps) & 1);
+    if (r->path == R_EULER) {  // every launch writes the other buffer
+      const int64_t ks = euler_steps_per_launch();
+      r->parity = static_cast<int>((r->parity + (r->tick_steps + ks - 1) / ks) & 1);
+    }
     s->stats.cell_updates += static_cast<double>(r->prob.n) * r->tick_steps;
   }
   s->stats.ticks++;
