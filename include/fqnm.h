@@ -205,6 +205,8 @@ fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u);
  * components (density-only Euler kinds: the density alone).  Syncs. */
 fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out);
 
+/* The context's launch plan.  Euler contexts have a fixed one and report
+ * kernel 0 with depth = the steps advanced per launch (8). */
 fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out);
 /* Force a plan (zero fields keep the current choice).  FQNM_ERR_ARG if the
  * combination is not available for this problem. */
