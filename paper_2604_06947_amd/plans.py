@@ -8,7 +8,7 @@ BENCH_PLAN_W2 = (KERNEL_TBLOCK, 4, 48)
 # near-Nyquist advection, 2^24 int64 cells, 2000 steps
 BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
 # the one-step-per-pass streaming plan reported beside it
-STREAM_PLAN_W3 = (KERNEL_STREAM, 2, 1)
+STREAM_PLAN_W3 = (KERNEL_STREAM, 4, 1)
 
 # HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain device copy of known size (see profiles/).

@@ -344,11 +344,14 @@ def test_w2_full_size_overlapping_windows_sampled():
 
 
 @pytest.mark.parametrize("r", [1e-2, 1e-3, 1e-4])
-def test_w3_nyquist_full_size_sampled(r):
+@pytest.mark.parametrize("which", ["blocked", "streaming"])
+def test_w3_nyquist_full_size_sampled(r, which):
+    # both plans the benchmark times on this workload
     from paper_2604_06947_amd import plans
+    plan = plans.BENCH_PLAN_W3 if which == "blocked" else plans.STREAM_PLAN_W3
     w = W.w3_nyquist_advection(r=r)
     prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I64, a=1.0)
-    q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plans.BENCH_PLAN_W3)
+    q, inv = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
     q0 = O.quantise(w.u0, w.delta, 64)
     assert inv["sum"][0] == int(q0.sum())
     op = O.Problem(O.UPWIND, w.delta, w.lam, width=64, a=1.0)
