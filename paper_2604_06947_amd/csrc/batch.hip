@@ -46,8 +46,9 @@ __device__ __forceinline__ void maps32(const XParams& P, int32_t q, int32_t& pp,
 }
 
 template <int POL, int V>
-__device__ void run_resident(const BInst& I, int32_t* __restrict__ state, int32_t* s_first,
-                             int32_t* s_last, int32_t* s_q0, int32_t* s_qn1) {
+__device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict__ state,
+                                             int32_t* s_first, int32_t* s_last, int32_t* s_q0,
+                                             int32_t* s_qn1) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = I.n;
   const int L = (n + V - 1) / V;  // lanes in use
@@ -126,8 +127,8 @@ __device__ void run_resident(const BInst& I, int32_t* __restrict__ state, int32_
 }
 
 template <int POL>
-__device__ void run_by_vec(const BInst& I, int32_t* state, int32_t* a, int32_t* b, int32_t* c,
-                           int32_t* d) {
+__device__ __forceinline__ void run_by_vec(const BInst& I, int32_t* state, int32_t* a,
+                                           int32_t* b, int32_t* c, int32_t* d) {
   switch (I.vec) {
     case 2: run_resident<POL, 2>(I, state, a, b, c, d); break;
     case 4: run_resident<POL, 4>(I, state, a, b, c, d); break;
@@ -153,10 +154,11 @@ __global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
     __syncthreads();
-    const int32_t k = s_next;
+    // uniform: the instance record is read by scalar loads and kept in SGPRs
+    const int32_t k = __builtin_amdgcn_readfirstlane(s_next);
     __syncthreads();
     if (k >= count) return;  // every workgroup leaves once the counter passes the end
-    const BInst I = insts[order[k]];
+    const BInst I = insts[__builtin_amdgcn_readfirstlane(order[k])];
     switch (I.pol) {
       case P_UPWIND_POS: run_by_vec<P_UPWIND_POS>(I, state, s_first, s_last, s_q0, s_qn1); break;
       case P_UPWIND_NEG: run_by_vec<P_UPWIND_NEG>(I, state, s_first, s_last, s_q0, s_qn1); break;
