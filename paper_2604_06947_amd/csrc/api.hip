@@ -362,6 +362,7 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     ctx->xp.lut = ctx->d_lut;
     ctx->xp.lut_lo = lo;
     ctx->xp.lut_last = count - 1;
+    ctx->xp.lut_pol = direct_split_policy(p);
   }
   ctx->pol = policy_of(p, lut);
   ctx->direct_pol = policy_of(p, false);

@@ -41,8 +41,7 @@ using BInst = ResidentInst;
 
 template <int POL>
 __device__ __forceinline__ void maps32(const XParams& P, int32_t q, int32_t& pp, int32_t& pm) {
-  pp = split_phi<int32_t, POL>(P, q, true);
-  pm = split_phi<int32_t, POL>(P, q, false);
+  split_maps<int32_t, POL>(P, q, pp, pm);
 }
 
 template <int POL, int V>

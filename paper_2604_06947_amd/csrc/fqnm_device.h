@@ -38,6 +38,7 @@ struct XParams {
   const void* lut;  // P_LUT: int2 (I32) or longlong2 (I64) entries {phi+(q), phi-(q)}
   int64_t lut_lo;   // first tabulated state
   int64_t lut_last; // number of entries - 1
+  int32_t lut_pol;  // P_LUT: the direct split policy whose maps the table holds
 };
 
 // For 64-bit states the conversions use the bias B = 1.5*2^52: for |v| < 2^51
@@ -122,6 +123,22 @@ __device__ __forceinline__ IT split_phi(const XParams& P, IT q, bool plus) {
   } else {
     static_assert(POL == P_LF_BURGERS, "not a direct split policy");
     return lf_phi<IT>(P, q, plus, false);
+  }
+}
+
+// Both split maps of one state.  For Engquist-Osher only one of them can be
+// nonzero (the sign of q decides), so one rounded product serves both: the
+// other map is rint(0) = 0, the value its own evaluation gives.
+template <typename IT, int POL>
+__device__ __forceinline__ void split_maps(const XParams& P, IT q, IT& pp, IT& pm) {
+  if constexpr (POL == P_EO) {
+    const IT t = round_to<IT>(P.h * square_f64<IT>(q));
+    const bool pos = q > IT(0);
+    pp = pos ? t : IT(0);
+    pm = pos ? IT(0) : t;
+  } else {
+    pp = split_phi<IT, POL>(P, q, true);
+    pm = split_phi<IT, POL>(P, q, false);
   }
 }
 

@@ -107,8 +107,7 @@ __device__ __forceinline__ void cell_maps(const XParams& P, const LutView& L, IT
       pm = static_cast<IT>(e.y);
     }
   } else {
-    pp = split_phi<IT, POL>(P, q, true);
-    pm = split_phi<IT, POL>(P, q, false);
+    split_maps<IT, POL>(P, q, pp, pm);
   }
 }
 
@@ -317,6 +316,19 @@ __device__ __forceinline__ void tb_step_addr(uint32_t (&a)[V], uint32_t end) {
   for (int j = 0; j < V; ++j) a[j] += ((j == 0 ? Fl : F[j - 1]) - F[j]) << 3;
 }
 
+// ksteps steps of a wavefront window with no LDS table slice.
+template <typename IT, int POL, int V>
+__device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView& L, IT (&q)[V],
+                                                int64_t g0, int64_t n, bool plain, bool own_right,
+                                                int ksteps, long long& led) {
+  const LdsWindow Wn{0u, 0u};
+  if (plain) {
+    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
+  } else {
+    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, Wn, q, g0, n, own_right, led);
+  }
+}
+
 template <typename IT, int POL, int V>
 __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* __restrict__ dst,
                                                 int64_t n, int bc, int ksteps, int khalo,
@@ -397,11 +409,23 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
     }
   }
   if (!done) {
-    const LdsWindow Wn{0u, 0u};
-    if (plain) {
-      for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
+    if constexpr (POL == P_LUT && sizeof(IT) == 4) {
+      // The tile's states span more than the window (a shock inside it): the
+      // split maps the table was built from give the same entries without a
+      // dependent L2 read on every step.
+      switch (P.lut_pol) {
+        case P_UPWIND_POS:
+          tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          break;
+        case P_UPWIND_NEG:
+          tb_steps_direct<IT, P_UPWIND_NEG, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          break;
+        default:
+          tb_steps_direct<IT, P_EO, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          break;
+      }
     } else {
-      for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, Wn, q, g0, n, own_right, led);
+      tb_steps_direct<IT, POL, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
     }
   }
   const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;

@@ -92,6 +92,7 @@ def make_case(flux, bc, itype, n, seed, a=1.0, alpha=0.0, lut=False):
 
 
 KINDS = [(F.FLUX_UPWIND, 1.0, False), (F.FLUX_UPWIND, -0.9, False), (F.FLUX_UPWIND, 1.0, True),
+         (F.FLUX_UPWIND, -0.9, True),
          (F.FLUX_BURGERS_EO, 1.0, False), (F.FLUX_BURGERS_EO, 1.0, True),
          (F.FLUX_BURGERS_GODUNOV, 1.0, False), (F.FLUX_BURGERS_MURMAN_ROE, 1.0, False),
          (F.FLUX_LF_LINEAR, 0.6, False), (F.FLUX_LF_BURGERS, 1.0, False)]
