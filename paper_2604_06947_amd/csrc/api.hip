@@ -247,7 +247,7 @@ fqnm_plan default_plan(const fqnm_problem& p) {
   fqnm_plan pl;
   pl.kernel = K_TBLOCK;
   pl.vec = p.itype == FQNM_I32 ? 4 : 8;
-  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 48 : 24;
+  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 40 : 24;
   pl.eval = 0;
   return pl;
 }
@@ -907,7 +907,7 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     if (ctx->dim > 1) break;
     const int PER = i32 ? 4 : 2;
     if (v >= 2 * PER) cand.push_back({K_STREAM, v, 1, 0});
-    for (int d : {4, 8, 16, 32, 64, 96}) {
+    for (int d : {4, 8, 16, 32, 40, 48, 64, 96}) {
       const int kh = scalar_halo(K_TBLOCK, v, d);
       if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
     }
