@@ -125,25 +125,35 @@ __device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict
   }
 }
 
-template <int POL>
+// The variants with 64 and 128 cells per lane hold them in registers and need
+// more than 128 VGPRs, which would hold every other variant to one workgroup
+// per CU.  They therefore run in a kernel of their own (WIDE), beside a kernel
+// for the narrower variants that fits more workgroups per CU; each kernel
+// takes the instances of its own class.  The 128-cell variant is built for
+// the split kinds only (two-point kinds need more temporaries and stop at 64).
+constexpr int BWIDE = 64;  // narrowest variant of the wide kernel
+
+template <int POL, bool WIDE>
 __device__ __forceinline__ void run_by_vec(const BInst& I, int32_t* state, int32_t* a,
                                            int32_t* b, int32_t* c, int32_t* d) {
-  switch (I.vec) {
-    case 2: run_resident<POL, 2>(I, state, a, b, c, d); break;
-    case 4: run_resident<POL, 4>(I, state, a, b, c, d); break;
-    case 8: run_resident<POL, 8>(I, state, a, b, c, d); break;
-    case 16: run_resident<POL, 16>(I, state, a, b, c, d); break;
-    case 32: run_resident<POL, 32>(I, state, a, b, c, d); break;
-    case 64: run_resident<POL, 64>(I, state, a, b, c, d); break;
-    default:
-      // the widest variant keeps 128 cells per lane in registers; it is built
-      // for the split kinds only (two-point kinds need more temporaries and
-      // stop at 64, their larger instances use the single-grid stepper)
+  if constexpr (WIDE) {
+    if (I.vec == 64) {
+      run_resident<POL, 64>(I, state, a, b, c, d);
+    } else {
       if constexpr (IsSplit<POL>::value) run_resident<POL, 128>(I, state, a, b, c, d);
-      break;
+    }
+  } else {
+    switch (I.vec) {
+      case 2: run_resident<POL, 2>(I, state, a, b, c, d); break;
+      case 4: run_resident<POL, 4>(I, state, a, b, c, d); break;
+      case 8: run_resident<POL, 8>(I, state, a, b, c, d); break;
+      case 16: run_resident<POL, 16>(I, state, a, b, c, d); break;
+      default: run_resident<POL, 32>(I, state, a, b, c, d); break;
+    }
   }
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__ insts,
                                                        const int32_t* __restrict__ order,
                                                        int32_t count, int32_t* counter,
@@ -158,19 +168,24 @@ __global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__
     __syncthreads();
     if (k >= count) return;  // every workgroup leaves once the counter passes the end
     const BInst I = insts[__builtin_amdgcn_readfirstlane(order[k])];
+    if ((I.vec >= BWIDE) != WIDE) continue;  // the other kernel's instance
     switch (I.pol) {
-      case P_UPWIND_POS: run_by_vec<P_UPWIND_POS>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      case P_UPWIND_NEG: run_by_vec<P_UPWIND_NEG>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      case P_EO: run_by_vec<P_EO>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      case P_GODUNOV: run_by_vec<P_GODUNOV>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      default: run_by_vec<P_MURMAN_ROE>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_UPWIND_POS:
+        run_by_vec<P_UPWIND_POS, WIDE>(I, state, s_first, s_last, s_q0, s_qn1);
+        break;
+      case P_UPWIND_NEG:
+        run_by_vec<P_UPWIND_NEG, WIDE>(I, state, s_first, s_last, s_q0, s_qn1);
+        break;
+      case P_EO: run_by_vec<P_EO, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_GODUNOV: run_by_vec<P_GODUNOV, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      default: run_by_vec<P_MURMAN_ROE, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
     }
     __syncthreads();
   }
 }
 
 __global__ void k_zero_counter(int32_t* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+  if (threadIdx.x < 2 && blockIdx.x == 0) c[threadIdx.x] = 0;
 }
 
 bool resident_policy(int pol) {
@@ -198,23 +213,74 @@ bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps) {
 
 int resident_vec(int64_t n) { return pick_vec(n, BT); }
 
-int resident_grid() {
+template <bool WIDE>
+int resident_grid_of() {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident, BT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident<WIDE>, BT, 0) !=
           hipSuccess || per_cu < 1)
     per_cu = 1;
   return std::max(1, cus * per_cu);
 }
 
+int32_t resident_wide_count(const ResidentInst* insts, int32_t count) {
+  int32_t w = 0;
+  for (int32_t i = 0; i < count; ++i) w += insts[i].vec >= BWIDE ? 1 : 0;
+  return w;
+}
+
+fqnm_status resident_launcher_init(ResidentLauncher* L) {
+  *L = ResidentLauncher{};
+  if (hipStreamCreateWithFlags(&L->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&L->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&L->join, hipEventDisableTiming) != hipSuccess)
+    return fail(FQNM_ERR_DEVICE, "resident launcher: stream/event creation failed");
+  if (hipMalloc(&L->d_counters, 2 * sizeof(int32_t)) != hipSuccess)
+    return fail(FQNM_ERR_OOM, "resident launcher: counter allocation failed");
+  return FQNM_OK;
+}
+
+void resident_launcher_free(ResidentLauncher* L) {
+  if (L->side) (void)hipStreamSynchronize(L->side);
+  if (L->d_counters) (void)hipFree(L->d_counters);
+  if (L->fork) (void)hipEventDestroy(L->fork);
+  if (L->join) (void)hipEventDestroy(L->join);
+  if (L->side) (void)hipStreamDestroy(L->side);
+  *L = ResidentLauncher{};
+}
+
 hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
-                           int32_t* d_counter, int32_t* d_state, hipStream_t s) {
+                           int32_t n_wide, const ResidentLauncher& L, int32_t* d_state,
+                           hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  k_zero_counter<<<1, 64, 0, s>>>(d_counter);
-  const int grid = std::min(resident_grid(), static_cast<int>(count));
-  k_batch_resident<<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count, d_counter, d_state);
-  return hipGetLastError();
+  const int32_t n_narrow = count - n_wide;
+  k_zero_counter<<<1, 64, 0, s>>>(L.d_counters);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool both = n_wide > 0 && n_narrow > 0;
+  if (both) {
+    // the narrow kernel runs beside the wide one on the side stream
+    if ((e = hipEventRecord(L.fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(L.side, L.fork, 0)) != hipSuccess) return e;
+  }
+  if (n_narrow > 0) {
+    const int grid = std::min(resident_grid_of<false>(), static_cast<int>(n_narrow));
+    k_batch_resident<false><<<dim3(grid), dim3(BT), 0, both ? L.side : s>>>(
+        d_insts, d_order, count, L.d_counters + 1, d_state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (n_wide > 0) {
+    const int grid = std::min(resident_grid_of<true>(), static_cast<int>(n_wide));
+    k_batch_resident<true><<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count,
+                                                           L.d_counters, d_state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (both) {
+    if ((e = hipEventRecord(L.join, L.side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, L.join, 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace fqnm
@@ -234,9 +300,9 @@ struct fqnm_batch {
   void* d_init = nullptr;
   BInst* d_insts = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_counter = nullptr;
+  ResidentLauncher launcher;
   int32_t n_resident = 0;
-  int grid = 0;
+  int32_t n_wide = 0;             // resident instances of the widest variant
   std::vector<fqnm_ctx*> big;    // fallback single-grid contexts (borrowing their slices)
   std::vector<int64_t> big_steps;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
@@ -259,7 +325,7 @@ static void batch_free(fqnm_batch* b) {
   if (b->d_init) (void)hipFree(b->d_init);
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_order) (void)hipFree(b->d_order);
-  if (b->d_counter) (void)hipFree(b->d_counter);
+  resident_launcher_free(&b->launcher);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -280,7 +346,7 @@ static fqnm_status batch_build_graph(fqnm_batch* b) {
   hipError_t e = hipSuccess;
   fqnm_status st = FQNM_OK;
   if (b->n_resident > 0)
-    e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->d_counter,
+    e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->n_wide, b->launcher,
                         static_cast<int32_t*>(b->d_state), b->stream);
   for (size_t i = 0; i < b->big.size() && e == hipSuccess && st == FQNM_OK; ++i)
     st = fqnm_step(b->big[i], b->big_steps[i]);
@@ -356,9 +422,9 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
     st = fail(FQNM_ERR_DEVICE, "stream/event creation failed");
   if (!st && (hipMalloc(&b->d_state, es * b->total) != hipSuccess ||
-              hipMalloc(&b->d_init, es * b->total) != hipSuccess ||
-              hipMalloc(&b->d_counter, sizeof(int32_t)) != hipSuccess))
+              hipMalloc(&b->d_init, es * b->total) != hipSuccess))
     st = fail(FQNM_ERR_OOM, "batch state allocation failed");
+  if (!st) st = resident_launcher_init(&b->launcher);
   for (int32_t k = 0; k < count && !st; ++k) {
     if (hipMemcpyAsync(static_cast<char*>(b->d_init) + es * b->off[k], q0s[k],
                        es * probs[k].n, hipMemcpyHostToDevice, b->stream) != hipSuccess)
@@ -384,7 +450,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
                 hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, b->stream) != hipSuccess))
       st = fail(FQNM_ERR_DEVICE, "copy batch table");
-    b->grid = std::min(resident_grid(), b->n_resident);
+    b->n_wide = resident_wide_count(host_insts.data(), b->n_resident);
   }
   // instances outside the resident envelope: single-grid contexts on their slices
   for (int32_t k = 0; k < count && !st; ++k) {

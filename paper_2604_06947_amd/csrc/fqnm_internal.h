@@ -149,9 +149,21 @@ struct ResidentInst {
 };
 bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps);
 int resident_vec(int64_t n);
-int resident_grid();
+// Launch state of the persistent batch kernels: the narrow-variant kernel runs
+// on `side`, forked from and joined back into the caller's stream by the two
+// events; d_counters holds the two kernels' work counters.
+struct ResidentLauncher {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int32_t* d_counters = nullptr;
+};
+fqnm_status resident_launcher_init(ResidentLauncher* L);
+void resident_launcher_free(ResidentLauncher* L);
+// instances among insts[0..count) that the wide kernel runs (64 or more cells per lane)
+int32_t resident_wide_count(const ResidentInst* insts, int32_t count);
 hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
-                           int32_t* d_counter, int32_t* d_state, hipStream_t s);
+                           int32_t n_wide, const ResidentLauncher& L, int32_t* d_state,
+                           hipStream_t s);
 
 // Thread-local error message of the public ABI.
 void set_error(const std::string& msg);

@@ -145,7 +145,7 @@ struct fqnm_server {
   // device tables (grown on demand)
   ResidentInst* d_rinst = nullptr;
   int32_t* d_rorder = nullptr;
-  int32_t* d_counter = nullptr;
+  ResidentLauncher launcher;
   size_t rcap = 0, ocap = 0;
   EulerReq* d_ereq = nullptr;
   size_t ecap = 0;
@@ -307,8 +307,9 @@ bool run_tick(fqnm_server* s) {
       e = hipMemcpyAsync(s->d_rorder, rorder.data(), sizeof(int32_t) * rorder.size(),
                          hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-      e = launch_resident(s->d_rinst, s->d_rorder, static_cast<int32_t>(ri.size()), s->d_counter,
-                          reinterpret_cast<int32_t*>(s->arena_base), s->stream);
+      e = launch_resident(s->d_rinst, s->d_rorder, static_cast<int32_t>(ri.size()),
+                          resident_wide_count(ri.data(), static_cast<int32_t>(ri.size())),
+                          s->launcher, reinterpret_cast<int32_t*>(s->arena_base), s->stream);
   }
   if (e == hipSuccess && !er.empty()) {
     if (!grow(&s->d_ereq, &s->ecap, er.size()) || !grow(&s->d_etile, &s->tcap, et.size())) {
@@ -428,7 +429,7 @@ void server_free(fqnm_server* s) {
   if (s->arena_base) (void)hipFree(s->arena_base);
   if (s->d_rinst) (void)hipFree(s->d_rinst);
   if (s->d_rorder) (void)hipFree(s->d_rorder);
-  if (s->d_counter) (void)hipFree(s->d_counter);
+  resident_launcher_free(&s->launcher);
   if (s->d_ereq) (void)hipFree(s->d_ereq);
   if (s->d_etile) (void)hipFree(s->d_etile);
   if (s->ev) (void)hipEventDestroy(s->ev);
@@ -458,10 +459,13 @@ fqnm_status fqnm_server_create(size_t device_budget_bytes, int32_t tick_steps, v
     server_free(s);
     return fail(FQNM_ERR_DEVICE, "stream/event creation failed");
   }
-  if (hipMalloc(&s->arena_base, device_budget_bytes) != hipSuccess ||
-      hipMalloc(&s->d_counter, sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc(&s->arena_base, device_budget_bytes) != hipSuccess) {
     server_free(s);
     return fail(FQNM_ERR_OOM, "server arena allocation failed");
+  }
+  if (fqnm_status st = resident_launcher_init(&s->launcher)) {
+    server_free(s);
+    return st;
   }
   s->arena.init(device_budget_bytes);
   s->worker = std::thread(worker_main, s);

@@ -85,6 +85,26 @@ def test_mixed_batch_matches_oracle_and_per_instance_loop():
         assert np.array_equal(solo[i], ref), i
 
 
+@pytest.mark.parametrize("sizes", [[5, 300, 1025, 4099, 16384], [16385, 32768, 40000, 65536]])
+def test_single_class_batches(sizes):
+    """Instances of at most 32 cells per lane run in one persistent kernel and
+    wider ones in another beside it; a batch holding only one of the two
+    classes launches that kernel alone."""
+    fluxes = [F.FLUX_UPWIND, F.FLUX_BURGERS_EO, F.FLUX_BURGERS_GODUNOV]
+    insts = [instance(k, n, 40 + 7 * k, fluxes[k % 3], F.BC_PERIODIC if k % 2 else F.BC_OUTFLOW,
+                      seed=3000 + k) for k, n in enumerate(sizes)]
+    probs = [p for p, _, _, _ in insts]
+    h = F.fqnm_batch_create(probs, [q.astype(np.int32) for _, q, _, _ in insts],
+                            [s for _, _, s, _ in insts])
+    try:
+        F.fqnm_batch_run(h)
+        got = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+    finally:
+        F.fqnm_batch_destroy(h)
+    for i, (p, q0, steps, op) in enumerate(insts):
+        assert np.array_equal(got[i], O.step(op, q0, steps)), (i, p.n, p.flux)
+
+
 def test_w4_sample_of_the_4096_instance_batch():
     """The first 48 instances of the seeded 4096-instance workload (full step
     counts) run as one batch must each equal the oracle."""
