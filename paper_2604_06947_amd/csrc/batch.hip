@@ -32,10 +32,14 @@
 namespace fqnm {
 namespace {
 
-constexpr int BT = 512;            // threads of the persistent workgroup
-constexpr int BW = BT / 64;        // wavefronts per workgroup
-constexpr int BMAXV = 128;         // largest cells-per-lane variant
-constexpr int64_t BMAXN = int64_t(BT) * BMAXV;
+constexpr int BT = 512;            // threads of a persistent workgroup (classes 0 and 1)
+constexpr int BT2 = 1024;          // threads of a class-2 workgroup
+constexpr int BMAXW = BT2 / 64;    // most wavefronts per workgroup
+constexpr int64_t BMAXN = int64_t(BT2) * 64;  // largest resident instance (split kinds)
+constexpr int64_t BMAXN2 = int64_t(BT2) * 32;  // largest resident instance (two-point kinds)
+
+template <int CLS>
+constexpr int threads_of() { return CLS == 2 ? BT2 : BT; }
 
 using BInst = ResidentInst;
 
@@ -44,7 +48,7 @@ __device__ __forceinline__ void maps32(const XParams& P, int32_t q, int32_t& pp,
   split_maps<int32_t, POL>(P, q, pp, pm);
 }
 
-template <int POL, int V>
+template <int POL, int V, int NW>
 __device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict__ state,
                                              int32_t* s_first, int32_t* s_last, int32_t* s_q0,
                                              int32_t* s_qn1) {
@@ -75,8 +79,8 @@ __device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict
     const int b = s & 1;
     const int32_t mylast = shortl ? q[V - 2 >= 0 ? V - 2 : 0] : q[V - 1];
     if (wave < wused) {
-      if (lane == 0) s_first[b * BW + wave] = q[0];
-      if (lane == 63) s_last[b * BW + wave] = mylast;
+      if (lane == 0) s_first[b * NW + wave] = q[0];
+      if (lane == 63) s_last[b * NW + wave] = mylast;
       if (tid == 0) s_q0[b] = q[0];
       if (tid == L - 1) s_qn1[b] = mylast;
     }
@@ -84,8 +88,8 @@ __device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict
     if (wave >= wused) continue;
     int32_t qp = __shfl_up(mylast, 1, 64);
     int32_t qn = __shfl_down(q[0], 1, 64);
-    if (lane == 0 && wave > 0) qp = s_last[b * BW + wave - 1];
-    if (lane == 63 && wave + 1 < BW) qn = s_first[b * BW + wave + 1];
+    if (lane == 0 && wave > 0) qp = s_last[b * NW + wave - 1];
+    if (lane == 63 && wave + 1 < NW) qn = s_first[b * NW + wave + 1];
     if (tid == 0) qp = periodic ? s_qn1[b] : q[0];      // ghost left of cell 0
     if (tid == L - 1) qn = periodic ? s_q0[b] : mylast;  // ghost right of cell n-1
     if constexpr (IsSplit<POL>::value) {
@@ -125,40 +129,43 @@ __device__ __forceinline__ void run_resident(const BInst& I, int32_t* __restrict
   }
 }
 
-// The variants with 64 and 128 cells per lane hold them in registers and need
-// more than 128 VGPRs, which would hold every other variant to one workgroup
-// per CU.  They therefore run in a kernel of their own (WIDE), beside a kernel
-// for the narrower variants that fits more workgroups per CU; each kernel
-// takes the instances of its own class.  The 128-cell variant is built for
-// the split kinds only (two-point kinds need more temporaries and stop at 64).
-constexpr int BWIDE = 64;  // narrowest variant of the wide kernel
-
-template <int POL, bool WIDE>
+// One persistent kernel per class of instance, so that the narrow variants
+// are not held to the occupancy of the widest.  Class 0: at most 16384 cells,
+// 512 threads, up to 32 cells per lane (86 VGPRs).  Class 1: split kinds of
+// 16385..32768 cells, 512 threads, 64 cells per lane (80 VGPRs).  Class 2:
+// larger split instances (64 cells per lane) and two-point instances above
+// 16384 cells (32 cells per lane), on 1024 threads, so that no variant keeps
+// more than 64 cells per lane in registers.  The kernels run side by side and
+// each takes the instances of its own class from the shared order.
+template <int POL, int CLS>
 __device__ __forceinline__ void run_by_vec(const BInst& I, int32_t* state, int32_t* a,
                                            int32_t* b, int32_t* c, int32_t* d) {
-  if constexpr (WIDE) {
-    if (I.vec == 64) {
-      run_resident<POL, 64>(I, state, a, b, c, d);
+  constexpr int NW = threads_of<CLS>() / 64;
+  if constexpr (CLS == 2) {
+    if constexpr (IsSplit<POL>::value) {
+      run_resident<POL, 64, NW>(I, state, a, b, c, d);
     } else {
-      if constexpr (IsSplit<POL>::value) run_resident<POL, 128>(I, state, a, b, c, d);
+      run_resident<POL, 32, NW>(I, state, a, b, c, d);
     }
+  } else if constexpr (CLS == 1) {
+    if constexpr (IsSplit<POL>::value) run_resident<POL, 64, NW>(I, state, a, b, c, d);
   } else {
     switch (I.vec) {
-      case 2: run_resident<POL, 2>(I, state, a, b, c, d); break;
-      case 4: run_resident<POL, 4>(I, state, a, b, c, d); break;
-      case 8: run_resident<POL, 8>(I, state, a, b, c, d); break;
-      case 16: run_resident<POL, 16>(I, state, a, b, c, d); break;
-      default: run_resident<POL, 32>(I, state, a, b, c, d); break;
+      case 2: run_resident<POL, 2, NW>(I, state, a, b, c, d); break;
+      case 4: run_resident<POL, 4, NW>(I, state, a, b, c, d); break;
+      case 8: run_resident<POL, 8, NW>(I, state, a, b, c, d); break;
+      case 16: run_resident<POL, 16, NW>(I, state, a, b, c, d); break;
+      default: run_resident<POL, 32, NW>(I, state, a, b, c, d); break;
     }
   }
 }
 
-template <bool WIDE>
-__global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__ insts,
-                                                       const int32_t* __restrict__ order,
-                                                       int32_t count, int32_t* counter,
-                                                       int32_t* __restrict__ state) {
-  __shared__ int32_t s_first[2 * BW], s_last[2 * BW], s_q0[2], s_qn1[2];
+template <int CLS>
+__global__ __launch_bounds__(threads_of<CLS>()) void k_batch_resident(
+    const BInst* __restrict__ insts, const int32_t* __restrict__ order, int32_t count,
+    int32_t* counter, int32_t* __restrict__ state) {
+  constexpr int NW = threads_of<CLS>() / 64;
+  __shared__ int32_t s_first[2 * NW], s_last[2 * NW], s_q0[2], s_qn1[2];
   __shared__ int32_t s_next;
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
@@ -168,24 +175,24 @@ __global__ __launch_bounds__(BT) void k_batch_resident(const BInst* __restrict__
     __syncthreads();
     if (k >= count) return;  // every workgroup leaves once the counter passes the end
     const BInst I = insts[__builtin_amdgcn_readfirstlane(order[k])];
-    if ((I.vec >= BWIDE) != WIDE) continue;  // the other kernel's instance
+    if (I.cls != CLS) continue;  // another kernel's instance
     switch (I.pol) {
       case P_UPWIND_POS:
-        run_by_vec<P_UPWIND_POS, WIDE>(I, state, s_first, s_last, s_q0, s_qn1);
+        run_by_vec<P_UPWIND_POS, CLS>(I, state, s_first, s_last, s_q0, s_qn1);
         break;
       case P_UPWIND_NEG:
-        run_by_vec<P_UPWIND_NEG, WIDE>(I, state, s_first, s_last, s_q0, s_qn1);
+        run_by_vec<P_UPWIND_NEG, CLS>(I, state, s_first, s_last, s_q0, s_qn1);
         break;
-      case P_EO: run_by_vec<P_EO, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      case P_GODUNOV: run_by_vec<P_GODUNOV, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
-      default: run_by_vec<P_MURMAN_ROE, WIDE>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_EO: run_by_vec<P_EO, CLS>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      case P_GODUNOV: run_by_vec<P_GODUNOV, CLS>(I, state, s_first, s_last, s_q0, s_qn1); break;
+      default: run_by_vec<P_MURMAN_ROE, CLS>(I, state, s_first, s_last, s_q0, s_qn1); break;
     }
     __syncthreads();
   }
 }
 
 __global__ void k_zero_counter(int32_t* c) {
-  if (threadIdx.x < 2 && blockIdx.x == 0) c[threadIdx.x] = 0;
+  if (threadIdx.x < RCLASSES && blockIdx.x == 0) c[threadIdx.x] = 0;
 }
 
 bool resident_policy(int pol) {
@@ -195,14 +202,14 @@ bool resident_policy(int pol) {
 
 // cells per lane for an instance of n cells with at most `lanes` lanes in use
 int pick_vec(int64_t n, int lanes) {
-  for (int v = 2; v <= BMAXV; v *= 2)
+  for (int v = 2; v < 64; v *= 2)
     if ((n + v - 1) / v <= lanes) return v;
-  return BMAXV;
+  return 64;
 }
 
-int64_t resident_max_n(int pol) {
-  return (pol == P_GODUNOV || pol == P_MURMAN_ROE) ? int64_t(BT) * 64 : BMAXN;
-}
+bool two_point(int pol) { return pol == P_GODUNOV || pol == P_MURMAN_ROE; }
+
+int64_t resident_max_n(int pol) { return two_point(pol) ? BMAXN2 : BMAXN; }
 
 }  // namespace
 
@@ -211,74 +218,107 @@ bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps) {
          resident_policy(pol) && steps <= INT32_MAX;
 }
 
-int resident_vec(int64_t n) { return pick_vec(n, BT); }
+void resident_layout(int64_t n, int pol, int32_t* vec, int32_t* cls) {
+  if (n <= int64_t(BT) * 32) {
+    *cls = 0;
+    *vec = pick_vec(n, BT);
+  } else if (!two_point(pol) && n <= int64_t(BT) * 64) {
+    *cls = 1;
+    *vec = 64;
+  } else {
+    *cls = 2;
+    *vec = pick_vec(n, BT2);
+  }
+}
 
-template <bool WIDE>
-int resident_grid_of() {
+int resident_grid_of(int cls) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident<WIDE>, BT, 0) !=
-          hipSuccess || per_cu < 1)
-    per_cu = 1;
+  hipError_t e = cls == 0   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident<0>, BT, 0)
+                 : cls == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident<1>, BT, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_resident<2>, BT2, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return std::max(1, cus * per_cu);
 }
 
-int32_t resident_wide_count(const ResidentInst* insts, int32_t count) {
-  int32_t w = 0;
-  for (int32_t i = 0; i < count; ++i) w += insts[i].vec >= BWIDE ? 1 : 0;
-  return w;
+void resident_class_counts(const ResidentInst* insts, int32_t count, int32_t* per_class) {
+  for (int c = 0; c < RCLASSES; ++c) per_class[c] = 0;
+  for (int32_t i = 0; i < count; ++i) ++per_class[insts[i].cls];
 }
 
 fqnm_status resident_launcher_init(ResidentLauncher* L) {
   *L = ResidentLauncher{};
-  if (hipStreamCreateWithFlags(&L->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&L->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&L->join, hipEventDisableTiming) != hipSuccess)
-    return fail(FQNM_ERR_DEVICE, "resident launcher: stream/event creation failed");
-  if (hipMalloc(&L->d_counters, 2 * sizeof(int32_t)) != hipSuccess)
+  for (int c = 0; c < RCLASSES - 1; ++c)
+    if (hipStreamCreateWithFlags(&L->side[c], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&L->join[c], hipEventDisableTiming) != hipSuccess)
+      return fail(FQNM_ERR_DEVICE, "resident launcher: stream/event creation failed");
+  if (hipEventCreateWithFlags(&L->fork, hipEventDisableTiming) != hipSuccess)
+    return fail(FQNM_ERR_DEVICE, "resident launcher: event creation failed");
+  if (hipMalloc(&L->d_counters, RCLASSES * sizeof(int32_t)) != hipSuccess)
     return fail(FQNM_ERR_OOM, "resident launcher: counter allocation failed");
   return FQNM_OK;
 }
 
 void resident_launcher_free(ResidentLauncher* L) {
-  if (L->side) (void)hipStreamSynchronize(L->side);
+  for (int c = 0; c < RCLASSES - 1; ++c)
+    if (L->side[c]) (void)hipStreamSynchronize(L->side[c]);
   if (L->d_counters) (void)hipFree(L->d_counters);
   if (L->fork) (void)hipEventDestroy(L->fork);
-  if (L->join) (void)hipEventDestroy(L->join);
-  if (L->side) (void)hipStreamDestroy(L->side);
+  for (int c = 0; c < RCLASSES - 1; ++c) {
+    if (L->join[c]) (void)hipEventDestroy(L->join[c]);
+    if (L->side[c]) (void)hipStreamDestroy(L->side[c]);
+  }
   *L = ResidentLauncher{};
 }
 
+static hipError_t launch_class(int cls, int grid, const ResidentInst* d_insts,
+                               const int32_t* d_order, int32_t count, int32_t* counter,
+                               int32_t* d_state, hipStream_t s) {
+  if (cls == 0)
+    k_batch_resident<0><<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count, counter, d_state);
+  else if (cls == 1)
+    k_batch_resident<1><<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count, counter, d_state);
+  else
+    k_batch_resident<2><<<dim3(grid), dim3(BT2), 0, s>>>(d_insts, d_order, count, counter, d_state);
+  return hipGetLastError();
+}
+
 hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
-                           int32_t n_wide, const ResidentLauncher& L, int32_t* d_state,
+                           const int32_t* per_class, const ResidentLauncher& L, int32_t* d_state,
                            hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const int32_t n_narrow = count - n_wide;
   k_zero_counter<<<1, 64, 0, s>>>(L.d_counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool both = n_wide > 0 && n_narrow > 0;
-  if (both) {
-    // the narrow kernel runs beside the wide one on the side stream
-    if ((e = hipEventRecord(L.fork, s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(L.side, L.fork, 0)) != hipSuccess) return e;
+  // the widest nonempty class runs on the caller's stream, launched last; the
+  // others run beside it on side streams forked from that stream and joined
+  // back into it, launched first so that they are not left only the CUs'
+  // leftover registers
+  int widest = -1;
+  for (int cls = 0; cls < RCLASSES; ++cls)
+    if (per_class[cls] > 0) widest = cls;
+  int used = 0;
+  for (int cls = 0; cls <= widest; ++cls) {
+    if (per_class[cls] <= 0 || cls == widest) continue;
+    if (used == 0 && (e = hipEventRecord(L.fork, s)) != hipSuccess) return e;
+    hipStream_t st = L.side[used];
+    if ((e = hipStreamWaitEvent(st, L.fork, 0)) != hipSuccess) return e;
+    const int grid = std::min(resident_grid_of(cls), static_cast<int>(per_class[cls]));
+    if ((e = launch_class(cls, grid, d_insts, d_order, count, L.d_counters + cls, d_state, st)) !=
+        hipSuccess)
+      return e;
+    ++used;
   }
-  if (n_narrow > 0) {
-    const int grid = std::min(resident_grid_of<false>(), static_cast<int>(n_narrow));
-    k_batch_resident<false><<<dim3(grid), dim3(BT), 0, both ? L.side : s>>>(
-        d_insts, d_order, count, L.d_counters + 1, d_state);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (widest >= 0) {
+    const int grid = std::min(resident_grid_of(widest), static_cast<int>(per_class[widest]));
+    if ((e = launch_class(widest, grid, d_insts, d_order, count, L.d_counters + widest, d_state,
+                          s)) != hipSuccess)
+      return e;
   }
-  if (n_wide > 0) {
-    const int grid = std::min(resident_grid_of<true>(), static_cast<int>(n_wide));
-    k_batch_resident<true><<<dim3(grid), dim3(BT), 0, s>>>(d_insts, d_order, count,
-                                                           L.d_counters, d_state);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  if (both) {
-    if ((e = hipEventRecord(L.join, L.side)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, L.join, 0)) != hipSuccess) return e;
+  for (int k = 0; k < used; ++k) {
+    if ((e = hipEventRecord(L.join[k], L.side[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, L.join[k], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -302,7 +342,7 @@ struct fqnm_batch {
   int32_t* d_order = nullptr;
   ResidentLauncher launcher;
   int32_t n_resident = 0;
-  int32_t n_wide = 0;             // resident instances of the widest variant
+  int32_t n_class[RCLASSES] = {}; // resident instances per persistent kernel
   std::vector<fqnm_ctx*> big;    // fallback single-grid contexts (borrowing their slices)
   std::vector<int64_t> big_steps;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
@@ -346,7 +386,7 @@ static fqnm_status batch_build_graph(fqnm_batch* b) {
   hipError_t e = hipSuccess;
   fqnm_status st = FQNM_OK;
   if (b->n_resident > 0)
-    e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->n_wide, b->launcher,
+    e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->n_class, b->launcher,
                         static_cast<int32_t*>(b->d_state), b->stream);
   for (size_t i = 0; i < b->big.size() && e == hipSuccess && st == FQNM_OK; ++i)
     st = fqnm_step(b->big[i], b->big_steps[i]);
@@ -406,7 +446,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       I.n = static_cast<int32_t>(p.n);
       I.steps = static_cast<int32_t>(steps[k]);
       I.pol = pol;
-      I.vec = resident_vec(p.n);
+      resident_layout(p.n, pol, &I.vec, &I.cls);
       I.bc = p.bc;
       XParams x = xparams_of(p);
       I.c = x.c;
@@ -450,7 +490,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
                 hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, b->stream) != hipSuccess))
       st = fail(FQNM_ERR_DEVICE, "copy batch table");
-    b->n_wide = resident_wide_count(host_insts.data(), b->n_resident);
+    resident_class_counts(host_insts.data(), b->n_resident, b->n_class);
   }
   // instances outside the resident envelope: single-grid contexts on their slices
   for (int32_t k = 0; k < count && !st; ++k) {

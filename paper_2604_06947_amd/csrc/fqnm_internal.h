@@ -143,26 +143,30 @@ struct ResidentInst {
   int32_t pol;
   int32_t vec;
   int32_t bc;
-  int32_t pad_;
+  int32_t cls;     // which persistent kernel runs it (resident_layout)
   double c;
   double h;
 };
 bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps);
-int resident_vec(int64_t n);
-// Launch state of the persistent batch kernels: the narrow-variant kernel runs
-// on `side`, forked from and joined back into the caller's stream by the two
-// events; d_counters holds the two kernels' work counters.
+// cells per lane and kernel class of a resident instance of n cells
+void resident_layout(int64_t n, int pol, int32_t* vec, int32_t* cls);
+// Launch state of the persistent batch kernels (one per register-footprint
+// class): the classes other than the widest nonempty one run on the side
+// streams, forked from the caller's stream by `fork` and joined back by
+// `join`; d_counters holds the kernels' work counters.
+constexpr int RCLASSES = 3;
 struct ResidentLauncher {
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t side[RCLASSES - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[RCLASSES - 1] = {};
   int32_t* d_counters = nullptr;
 };
 fqnm_status resident_launcher_init(ResidentLauncher* L);
 void resident_launcher_free(ResidentLauncher* L);
-// instances among insts[0..count) that the wide kernel runs (64 or more cells per lane)
-int32_t resident_wide_count(const ResidentInst* insts, int32_t count);
+// instances of each class among insts[0..count)
+void resident_class_counts(const ResidentInst* insts, int32_t count, int32_t* per_class);
 hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, int32_t count,
-                           int32_t n_wide, const ResidentLauncher& L, int32_t* d_state,
+                           const int32_t* per_class, const ResidentLauncher& L, int32_t* d_state,
                            hipStream_t s);
 
 // Thread-local error message of the public ABI.

@@ -259,7 +259,7 @@ bool run_tick(fqnm_server* s) {
       I.n = static_cast<int32_t>(r->prob.n);
       I.steps = static_cast<int32_t>(r->tick_steps);
       I.pol = r->pol;
-      I.vec = resident_vec(r->prob.n);
+      resident_layout(r->prob.n, r->pol, &I.vec, &I.cls);
       I.bc = r->prob.bc;
       XParams x = xparams_of(r->prob);
       I.c = x.c;
@@ -306,10 +306,12 @@ bool run_tick(fqnm_server* s) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->d_rorder, rorder.data(), sizeof(int32_t) * rorder.size(),
                          hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-      e = launch_resident(s->d_rinst, s->d_rorder, static_cast<int32_t>(ri.size()),
-                          resident_wide_count(ri.data(), static_cast<int32_t>(ri.size())),
+    if (e == hipSuccess) {
+      int32_t per_class[RCLASSES];
+      resident_class_counts(ri.data(), static_cast<int32_t>(ri.size()), per_class);
+      e = launch_resident(s->d_rinst, s->d_rorder, static_cast<int32_t>(ri.size()), per_class,
                           s->launcher, reinterpret_cast<int32_t*>(s->arena_base), s->stream);
+    }
   }
   if (e == hipSuccess && !er.empty()) {
     if (!grow(&s->d_ereq, &s->ecap, er.size()) || !grow(&s->d_etile, &s->tcap, et.size())) {

@@ -85,11 +85,16 @@ def test_mixed_batch_matches_oracle_and_per_instance_loop():
         assert np.array_equal(solo[i], ref), i
 
 
-@pytest.mark.parametrize("sizes", [[5, 300, 1025, 4099, 16384], [16385, 32768, 40000, 65536]])
-def test_single_class_batches(sizes):
-    """Instances of at most 32 cells per lane run in one persistent kernel and
-    wider ones in another beside it; a batch holding only one of the two
-    classes launches that kernel alone."""
+@pytest.mark.parametrize("sizes", [[5, 300, 1025, 4099, 16384], [20000, 30000], [40000, 65536],
+                                   [16385, 32768, 40000, 65536], [100, 200, 20000, 30000]])
+def test_batches_of_some_classes(sizes):
+    """Resident instances run in one of three persistent kernels launched side
+    by side: up to 16384 cells (512 threads); split kinds of 16385..32768 cells
+    (512 threads, 64 cells per lane); larger split instances and two-point
+    instances above 16384 cells (1024 threads).  Fluxes cycle upwind, EO,
+    Godunov.  Batches here hold only the first class, only the second, only
+    the third, the second and third with an instance routed to the
+    single-grid path (40000 cells of a two-point kind), and all three."""
     fluxes = [F.FLUX_UPWIND, F.FLUX_BURGERS_EO, F.FLUX_BURGERS_GODUNOV]
     insts = [instance(k, n, 40 + 7 * k, fluxes[k % 3], F.BC_PERIODIC if k % 2 else F.BC_OUTFLOW,
                       seed=3000 + k) for k, n in enumerate(sizes)]
