@@ -307,10 +307,13 @@ fqnm_status fqnm_step_transitions(fqnm_ctx* ctx, int64_t* from, int64_t* to, int
 
 /* ------------------------------------------------------------------------
  * Batching: many independent instances (each its own problem, state and step
- * count) advanced together.  Instances that fit one workgroup run every one
- * of their steps inside one persistent launch with their state held in
- * registers; larger ones use the single-grid stepper.  The whole run is
- * captured once as a HIP graph and replayed.
+ * count) advanced together.  int32 instances with direct evaluation and at
+ * most 65536 cells (32768 for the Godunov and Murman-Roe kinds) run every one
+ * of their steps inside persistent launches with their state held in
+ * registers: three kernels, one per size class, side by side on the caller's
+ * stream and two library streams forked from it and joined back.  Other
+ * instances use the single-grid stepper.  The whole run is captured once as a
+ * HIP graph and replayed.
  * ---------------------------------------------------------------------- */
 typedef struct fqnm_batch fqnm_batch;
 
