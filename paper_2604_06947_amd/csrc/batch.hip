@@ -291,17 +291,26 @@ hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, 
   k_zero_counter<<<1, 64, 0, s>>>(L.d_counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // the widest nonempty class runs on the caller's stream, launched last; the
-  // others run beside it on side streams forked from that stream and joined
-  // back into it, launched first so that they are not left only the CUs'
-  // leftover registers
-  int widest = -1;
+  // the widest nonempty class runs on the caller's stream and is launched
+  // first (its instances are the longest, so its workgroups should take the
+  // CUs first); the others run beside it on side streams forked from that
+  // stream before it and joined back into it after
+  int widest = -1, nonempty = 0;
   for (int cls = 0; cls < RCLASSES; ++cls)
-    if (per_class[cls] > 0) widest = cls;
+    if (per_class[cls] > 0) {
+      widest = cls;
+      ++nonempty;
+    }
+  if (nonempty > 1 && (e = hipEventRecord(L.fork, s)) != hipSuccess) return e;
+  if (widest >= 0) {
+    const int grid = std::min(resident_grid_of(widest), static_cast<int>(per_class[widest]));
+    if ((e = launch_class(widest, grid, d_insts, d_order, count, L.d_counters + widest, d_state,
+                          s)) != hipSuccess)
+      return e;
+  }
   int used = 0;
-  for (int cls = 0; cls <= widest; ++cls) {
-    if (per_class[cls] <= 0 || cls == widest) continue;
-    if (used == 0 && (e = hipEventRecord(L.fork, s)) != hipSuccess) return e;
+  for (int cls = widest - 1; cls >= 0; --cls) {
+    if (per_class[cls] <= 0) continue;
     hipStream_t st = L.side[used];
     if ((e = hipStreamWaitEvent(st, L.fork, 0)) != hipSuccess) return e;
     const int grid = std::min(resident_grid_of(cls), static_cast<int>(per_class[cls]));
@@ -309,12 +318,6 @@ hipError_t launch_resident(const ResidentInst* d_insts, const int32_t* d_order, 
         hipSuccess)
       return e;
     ++used;
-  }
-  if (widest >= 0) {
-    const int grid = std::min(resident_grid_of(widest), static_cast<int>(per_class[widest]));
-    if ((e = launch_class(widest, grid, d_insts, d_order, count, L.d_counters + widest, d_state,
-                          s)) != hipSuccess)
-      return e;
   }
   for (int k = 0; k < used; ++k) {
     if ((e = hipEventRecord(L.join[k], L.side[k])) != hipSuccess) return e;
