@@ -560,11 +560,23 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_wg(const int32_t* __restrict
       q[j] = static_cast<int32_t>(static_cast<uint32_t>(mn) +
                                   static_cast<uint32_t>(static_cast<int32_t>(a[j] - base) >> 3));
   } else {
+    // The workgroup's states span more than the staged slice: the split maps
+    // the table was built from give the same entries without a dependent L2
+    // read on every step.  (The switch is uniform over the workgroup, so
+    // every wavefront reaches the refresh barriers.)
     const LdsWindow Wn{0u, 0u};
     long long led = 0;
-    for (int s = 0; s < ksteps; ++s) {
-      tb_step<int32_t, P_LUT, V, false>(P, L, Wn, q, g0, n, false, led);
-      if ((s + 1) % WG_H == 0 && s + 1 < ksteps) refresh(q, ((s + 1) / WG_H) & 1);
+    auto run = [&](auto pol) {
+      constexpr int PD = decltype(pol)::value;
+      for (int s = 0; s < ksteps; ++s) {
+        tb_step<int32_t, PD, V, false>(P, L, Wn, q, g0, n, false, led);
+        if ((s + 1) % WG_H == 0 && s + 1 < ksteps) refresh(q, ((s + 1) / WG_H) & 1);
+      }
+    };
+    switch (P.lut_pol) {
+      case P_UPWIND_POS: run(std::integral_constant<int, P_UPWIND_POS>{}); break;
+      case P_UPWIND_NEG: run(std::integral_constant<int, P_UPWIND_NEG>{}); break;
+      default: run(std::integral_constant<int, P_EO>{}); break;
     }
   }
   // this wavefront's share of the stored cells
