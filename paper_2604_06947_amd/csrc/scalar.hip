@@ -783,14 +783,30 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
   }
   if (!done) {
     const LdsWindow Wn{0u, 0u};
-    if (plain) {
-      for (int s = 0; s < ksteps; ++s)
-        blk_step<IT, POL, V, NW, false, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
-                                               led);
+    auto run = [&](auto pol) {
+      constexpr int PD = decltype(pol)::value;
+      if (plain) {
+        for (int s = 0; s < ksteps; ++s)
+          blk_step<IT, PD, V, NW, false, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
+                                                led);
+      } else {
+        for (int s = 0; s < ksteps; ++s)
+          blk_step<IT, PD, V, NW, true, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
+                                               own_right, led);
+      }
+    };
+    if constexpr (POL == P_LUT && sizeof(IT) == 4) {
+      // The tile's states span more than the staged slice: the split maps the
+      // table was built from give the same entries without a dependent L2
+      // read on every step (the switch is uniform over the workgroup, so every
+      // wavefront reaches the per-step barriers).
+      switch (P.lut_pol) {
+        case P_UPWIND_POS: run(std::integral_constant<int, P_UPWIND_POS>{}); break;
+        case P_UPWIND_NEG: run(std::integral_constant<int, P_UPWIND_NEG>{}); break;
+        default: run(std::integral_constant<int, P_EO>{}); break;
+      }
     } else {
-      for (int s = 0; s < ksteps; ++s)
-        blk_step<IT, POL, V, NW, true, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
-                                              own_right, led);
+      run(std::integral_constant<int, POL>{});
     }
   }
   const int lo_t = khalo / V, hi_t = NW * 64 - khalo / V;
