@@ -409,10 +409,11 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
     }
   }
   if (!done) {
-    if constexpr (POL == P_LUT && sizeof(IT) == 4) {
-      // The tile's states span more than the window (a shock inside it): the
-      // split maps the table was built from give the same entries without a
-      // dependent L2 read on every step.
+    if constexpr (POL == P_LUT) {
+      // The tile's states span more than the window (a shock inside it), or
+      // the states are 64-bit (no LDS slice): the split maps the table was
+      // built from give the same entries without a dependent L2 read on every
+      // step.
       switch (P.lut_pol) {
         case P_UPWIND_POS:
           tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
