@@ -87,7 +87,13 @@ typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
  * modes produce the same integers.  LUT mode tabulates phi+ and phi- over the
  * initial state range [min q0, max q0], which bounds every later state by the
  * discrete maximum principle (Lemma cfl_monotone (i)); it is accepted for the
- * kinds for which that principle holds (UPWIND, BURGERS_EO). */
+ * kinds for which that principle holds (UPWIND, BURGERS_EO).  The
+ * temporally blocked kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
+ * from a per-tile slice in LDS when the tile's int32 states span fewer than
+ * 512 levels (2048 for tiles of several wavefronts); their wider int32 tiles
+ * and all their int64 tiles evaluate the maps the table was built from
+ * instead, which gives the same entries.  The other kernels read the table
+ * itself. */
 typedef enum { FQNM_EVAL_AUTO = 0, FQNM_EVAL_DIRECT = 1, FQNM_EVAL_LUT = 2 } fqnm_eval;
 
 /* Problem statement (Sec. 2): flux kind and its constants, resolution delta,

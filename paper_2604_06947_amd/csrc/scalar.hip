@@ -796,11 +796,12 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
                                                own_right, led);
       }
     };
-    if constexpr (POL == P_LUT && sizeof(IT) == 4) {
-      // The tile's states span more than the staged slice: the split maps the
-      // table was built from give the same entries without a dependent L2
-      // read on every step (the switch is uniform over the workgroup, so every
-      // wavefront reaches the per-step barriers).
+    if constexpr (POL == P_LUT) {
+      // The tile's states span more than the staged slice, or the states are
+      // 64-bit (no staged slice): the split maps the table was built from give
+      // the same entries without a dependent L2 read on every step (the
+      // switch is uniform over the workgroup, so every wavefront reaches the
+      // per-step barriers).
       switch (P.lut_pol) {
         case P_UPWIND_POS: run(std::integral_constant<int, P_UPWIND_POS>{}); break;
         case P_UPWIND_NEG: run(std::integral_constant<int, P_UPWIND_NEG>{}); break;

@@ -15,7 +15,7 @@ STREAM_PLAN_W3 = (KERNEL_STREAM, 4, 1)
 # Valid only for the kernel sources they were measured on: the benchmark
 # reports null when the hash of those sources differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
-MEASURED_SOURCES_SHA = "62ae0598686c44c0"
+MEASURED_SOURCES_SHA = "cce23d36ccc8e6ea"
 TRAFFIC_BYTES_PER_LAUNCH = {
     "w2": 11415 * 1024,  # k_tblock<int, P_LUT, 4>, 40 steps per launch
     "w6": 153359 * 1024,  # k_nd_tb<int, P_EO, 2, 4, true>, 24 rows per wavefront, 4 steps
