@@ -36,6 +36,9 @@
  * rounding mode), the rounding of the NumPy prototype the paper describes.
  */
 #include <fenv.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -202,6 +205,18 @@ int ofq_interface_flux(const ofq_problem* p, int64_t qL, int64_t qR, int64_t* F)
   return interface_flux(p, qL, qR, F);
 }
 
+/* Threads the stepping loops use: 1 in the plain build, the OpenMP team size
+ * in the build with -fopenmp (same source; every parallel loop runs over
+ * cells or interfaces that read only the state before the step, so both
+ * builds give the same integers). */
+int ofq_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 static int scalar_kind(int32_t k) {
   return k == OFQ_UPWIND || k == OFQ_BURGERS_EO || k == OFQ_BURGERS_GODUNOV ||
          k == OFQ_LF_LINEAR || k == OFQ_LF_BURGERS || k == OFQ_BURGERS_MURMAN_ROE;
@@ -246,11 +261,16 @@ void ofq_reconstruct(const int64_t* q, int64_t n, double delta, double* u) {
  * The ledger accumulates F[0] - F[n], the net count that entered the domain.
  * ------------------------------------------------------------------------- */
 static int scalar_step(const ofq_problem* p, int64_t n, int64_t* q, int64_t* F, int64_t* ledger) {
-  int st;
+  int err = OFQ_OK;
+  /* every interface reads the state before the step only, so the interfaces
+   * (and, below, the cells) are independent of one another */
+#pragma omp parallel for schedule(static) reduction(max : err)
   for (int64_t j = 1; j < n; ++j) {
-    st = interface_flux(p, q[j - 1], q[j], &F[j]);
-    if (st) return st;
+    int st = interface_flux(p, q[j - 1], q[j], &F[j]);
+    if (st > err) err = st;
   }
+  if (err) return err;
+  int st;
   if (p->bc == OFQ_BC_PERIODIC) {
     st = interface_flux(p, q[n - 1], q[0], &F[0]);
     if (st) return st;
@@ -261,13 +281,15 @@ static int scalar_step(const ofq_problem* p, int64_t n, int64_t* q, int64_t* F, 
     st = interface_flux(p, q[n - 1], q[n - 1], &F[n]);
     if (st) return st;
   }
+#pragma omp parallel for schedule(static) reduction(max : err)
   for (int64_t i = 0; i < n; ++i) {
     int64_t d = F[i + 1] - F[i];
-    if (!fits(p, d)) return OFQ_E_RANGE;
+    if (!fits(p, d)) { err = OFQ_E_RANGE; continue; }
     int64_t v = q[i] - d;
-    if (!fits(p, v)) return OFQ_E_RANGE;
+    if (!fits(p, v)) { err = OFQ_E_RANGE; continue; }
     q[i] = v;
   }
+  if (err) return err;
   if (ledger) *ledger += F[0] - F[n];
   return OFQ_OK;
 }
@@ -321,8 +343,13 @@ int ofq_step_nd(const ofq_problem* axes, int32_t dim, const int64_t* shape, int6
   int st = OFQ_OK;
   for (int64_t s = 0; s < nsteps && st == OFQ_OK; ++s) {
     memcpy(old, q, sizeof(int64_t) * (size_t)n);
-    for (int64_t i = 0; i < n && st == OFQ_OK; ++i) {
+    int err = OFQ_OK;
+    int64_t led = 0;
+    /* every cell reads the state before the step only */
+#pragma omp parallel for schedule(static) reduction(max : err) reduction(+ : led)
+    for (int64_t i = 0; i < n; ++i) {
       int64_t v = old[i];
+      int sti = OFQ_OK;
       for (int32_t m = 0; m < dim; ++m) {
         const ofq_problem* p = &axes[m];
         const int64_t im = (i / stride[m]) % shape[m];
@@ -332,21 +359,24 @@ int ofq_step_nd(const ofq_problem* axes, int32_t dim, const int64_t* shape, int6
         if (im < shape[m] - 1) hi_nb = i + stride[m];
         else hi_nb = p->bc == OFQ_BC_PERIODIC ? i - (shape[m] - 1) * stride[m] : i;
         int64_t Fhi, Flo;
-        st = interface_flux(p, old[i], old[hi_nb], &Fhi);
-        if (st) break;
-        st = interface_flux(p, old[lo_nb], old[i], &Flo);
-        if (st) break;
+        sti = interface_flux(p, old[i], old[hi_nb], &Fhi);
+        if (sti) break;
+        sti = interface_flux(p, old[lo_nb], old[i], &Flo);
+        if (sti) break;
         const int64_t d = Fhi - Flo;
-        if (!fits(p, d)) { st = OFQ_E_RANGE; break; }
+        if (!fits(p, d)) { sti = OFQ_E_RANGE; break; }
         v -= d;
-        if (!fits(p, v)) { st = OFQ_E_RANGE; break; }
-        if (ledger && p->bc == OFQ_BC_OUTFLOW) {
-          if (im == 0) *ledger += Flo;
-          if (im == shape[m] - 1) *ledger -= Fhi;
+        if (!fits(p, v)) { sti = OFQ_E_RANGE; break; }
+        if (p->bc == OFQ_BC_OUTFLOW) {
+          if (im == 0) led += Flo;
+          if (im == shape[m] - 1) led -= Fhi;
         }
       }
+      if (sti) { if (sti > err) err = sti; continue; }
       q[i] = v;
     }
+    st = err;
+    if (!st && ledger) *ledger += led;
   }
   free(old);
   return st;
@@ -633,19 +663,30 @@ int ofq_step_euler(const ofq_problem* p, int64_t n, int64_t* qr, int64_t* qm, in
   int64_t* q[3] = {qr, qm, qE};
   st = OFQ_OK;
   for (int64_t s = 0; s < nsteps && st == OFQ_OK; ++s) {
+    int err = OFQ_OK;
+    /* per cell: primitives of the state before the step */
+#pragma omp parallel for schedule(static) reduction(max : err)
     for (int64_t i = 0; i < n; ++i) {
-      for (int c = 0; c < 3; ++c) {
+      int sti = OFQ_OK;
+      for (int c = 0; c < 3 && !sti; ++c) {
         double x;
-        if ((st = to_double_exact(q[c][i], &x))) goto done;
+        sti = to_double_exact(q[c][i], &x);
       }
+      if (sti) { if (sti > err) err = sti; continue; }
       euler_cell(p->delta, g1, fix, qr[i], qm[i], qE[i], &cell[i]);
-      if (!(cell[i].r > 0.0) || !(cell[i].p > 0.0)) { st = OFQ_E_NONFINITE; goto done; }
+      if (!(cell[i].r > 0.0) || !(cell[i].p > 0.0)) err = OFQ_E_NONFINITE;
     }
-    double F[3];
+    if ((st = err)) goto done;
+    /* per interface: the Roe flux and its three rounded transfers */
+#pragma omp parallel for schedule(static) reduction(max : err)
     for (int64_t j = 1; j < n; ++j) {
-      roe_interface(g1, fix, &cell[j - 1], &cell[j], F, NULL);
-      if ((st = euler_transfer(p, F, &T[3 * j]))) goto done;
+      double Fj[3];
+      roe_interface(g1, fix, &cell[j - 1], &cell[j], Fj, NULL);
+      int sti = euler_transfer(p, Fj, &T[3 * j]);
+      if (sti > err) err = sti;
     }
+    if ((st = err)) goto done;
+    double F[3];
     if (p->bc == OFQ_BC_PERIODIC) {
       roe_interface(g1, fix, &cell[n - 1], &cell[0], F, NULL);
       if ((st = euler_transfer(p, F, &T[0]))) goto done;
@@ -656,14 +697,18 @@ int ofq_step_euler(const ofq_problem* p, int64_t n, int64_t* qr, int64_t* qm, in
       roe_interface(g1, fix, &cell[n - 1], &cell[n - 1], F, NULL);
       if ((st = euler_transfer(p, F, &T[3 * n]))) goto done;
     }
+    /* per cell: the telescoping update of each component */
+#pragma omp parallel for schedule(static) reduction(max : err)
     for (int64_t i = 0; i < n; ++i) {
       for (int c = 0; c < 3; ++c) {
         int64_t d = T[3 * (i + 1) + c] - T[3 * i + c];
+        if (!fits(p, d)) { err = OFQ_E_RANGE; break; }
         int64_t v = q[c][i] - d;
-        if (!fits(p, d) || !fits(p, v)) { st = OFQ_E_RANGE; goto done; }
+        if (!fits(p, v)) { err = OFQ_E_RANGE; break; }
         q[c][i] = v;
       }
     }
+    if ((st = err)) goto done;
     if (ledger)
       for (int c = 0; c < 3; ++c) ledger[c] += T[c] - T[3 * n + c];
   }
