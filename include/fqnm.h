@@ -211,6 +211,19 @@ fqnm_status fqnm_reconstruct_device(fqnm_ctx* ctx, double* d_u);
  * components (density-only Euler kinds: the density alone).  Syncs. */
 fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * same results as fqnm_invariants_get, with no device allocation.  The
+ * per-block partial records live in a static device array of the library
+ * (4099 records of 48 bytes, 192 KiB per device, held until the process ends)
+ * instead of a buffer the context allocates on first use; one block reduces
+ * ceil(n/4096) cells (at least 16384), so every context size fits.  Calls of
+ * one process are serialised by the library (the array is shared by all calls
+ * on a device).  Switches to the context's device for the call.  Syncs.
+ * FQNM_ERR_UNSUPPORTED for FP64 twin contexts, FQNM_ERR_RANGE should a state
+ * need more than 4096 partial records. */
+fqnm_status fqnm_invariants_get_noalloc(fqnm_ctx* ctx, fqnm_invariants* out);
+
 /* The context's launch plan.  Euler contexts have a fixed one and report
  * kernel 0 with depth = the steps advanced per launch (8). */
 fqnm_status fqnm_get_plan(fqnm_ctx* ctx, fqnm_plan* out);

@@ -382,6 +382,7 @@ static fqnm_status ctx_new(const fqnm_problem* prob, void* stream, fqnm_ctx** ou
   fqnm_ctx* ctx = new fqnm_ctx();
   ctx->prob = *prob;
   ctx->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&ctx->device) != hipSuccess) ctx->device = 0;
   ctx->euler = is_euler(prob->flux);
   ctx->comp = ctx->euler ? 3 : 1;
   ctx->esize = prob->itype == FQNM_I32 ? 4 : 8;

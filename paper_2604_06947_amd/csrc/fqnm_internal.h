@@ -96,6 +96,13 @@ hipError_t launch_reconstruct(int itype, const void* q, double* u, int64_t n, do
 int64_t reduce_blocks(int64_t n);
 hipError_t launch_reduce(int itype, const void* q, int64_t n, int periodic, ReducePartial* out,
                          hipStream_t s);
+// The same with cpb cells per block (ceil(n / cpb) partials), and the
+// combination of count partials into one record out[0].
+int64_t reduce_min_cells_per_block();
+hipError_t launch_reduce_cpb(int itype, const void* q, int64_t n, int periodic, int64_t cpb,
+                             ReducePartial* out, hipStream_t s);
+hipError_t launch_reduce_final(const ReducePartial* in, int count, ReducePartial* out,
+                               hipStream_t s);
 
 // Euler (3 x 8-byte components, structure of arrays): one step per launch.
 struct EulerParams {

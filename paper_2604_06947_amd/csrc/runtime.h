@@ -15,6 +15,7 @@ struct fqnm_ctx {
   int comp = 1;        // components per cell
   size_t esize = 4;    // bytes per integer
   hipStream_t stream = nullptr;
+  int device = 0;      // HIP device current at create
   void* buf[2] = {nullptr, nullptr};  // ping-pong states (buf[0] may be borrowed)
   bool borrowed = false;
   int cur = 0;                       // buffer holding the current state

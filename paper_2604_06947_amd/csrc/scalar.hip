@@ -970,17 +970,18 @@ __global__ void k_reconstruct(const IT* __restrict__ q, double* __restrict__ u, 
 constexpr int RED_THREADS = 256;
 constexpr int64_t RED_CELLS_PER_BLOCK = 256 * 64;
 
-// Exact sum (128-bit), min, max and total variation of one state.
+// Exact sum (128-bit), min, max and total variation of one state: block b
+// reduces cells [b*cpb, min((b+1)*cpb, n)) into out[b].
 template <typename IT>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const IT* __restrict__ q, int64_t n,
-                                                        int periodic,
+                                                        int periodic, int64_t cpb,
                                                         ReducePartial* __restrict__ out) {
   __shared__ __int128 s_sum[RED_THREADS];
   __shared__ __int128 s_tv[RED_THREADS];
   __shared__ int64_t s_min[RED_THREADS];
   __shared__ int64_t s_max[RED_THREADS];
-  const int64_t b0 = blockIdx.x * RED_CELLS_PER_BLOCK;
-  const int64_t b1 = b0 + RED_CELLS_PER_BLOCK < n ? b0 + RED_CELLS_PER_BLOCK : n;
+  const int64_t b0 = blockIdx.x * cpb;
+  const int64_t b1 = b0 + cpb < n ? b0 + cpb : n;
   __int128 sum = 0, tv = 0;
   int64_t mn = INT64_MAX, mx = INT64_MIN;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += RED_THREADS) {
@@ -1023,6 +1024,52 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const IT* __restrict__ q
     r.qmin = s_min[0];
     r.qmax = s_max[0];
     out[blockIdx.x] = r;
+  }
+}
+
+// Combines count >= 1 partial records into out[0] (one block; exact integer
+// sums, so the order does not matter).
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const ReducePartial* __restrict__ in,
+                                                              int count,
+                                                              ReducePartial* __restrict__ out) {
+  __shared__ __int128 s_sum[RED_THREADS];
+  __shared__ __int128 s_tv[RED_THREADS];
+  __shared__ int64_t s_min[RED_THREADS];
+  __shared__ int64_t s_max[RED_THREADS];
+  __int128 sum = 0, tv = 0;
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+  for (int i = threadIdx.x; i < count; i += RED_THREADS) {
+    const ReducePartial r = in[i];
+    sum += (static_cast<__int128>(r.sum_hi) << 64) | r.sum_lo;
+    tv += (static_cast<__int128>(r.tv_hi) << 64) | r.tv_lo;
+    mn = r.qmin < mn ? r.qmin : mn;
+    mx = r.qmax > mx ? r.qmax : mx;
+  }
+  s_sum[threadIdx.x] = sum;
+  s_tv[threadIdx.x] = tv;
+  s_min[threadIdx.x] = mn;
+  s_max[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+      s_tv[threadIdx.x] += s_tv[threadIdx.x + w];
+      s_min[threadIdx.x] = s_min[threadIdx.x + w] < s_min[threadIdx.x] ? s_min[threadIdx.x + w]
+                                                                       : s_min[threadIdx.x];
+      s_max[threadIdx.x] = s_max[threadIdx.x + w] > s_max[threadIdx.x] ? s_max[threadIdx.x + w]
+                                                                       : s_max[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ReducePartial r;
+    r.sum_lo = static_cast<uint64_t>(s_sum[0]);
+    r.sum_hi = static_cast<int64_t>(s_sum[0] >> 64);
+    r.tv_lo = static_cast<uint64_t>(s_tv[0]);
+    r.tv_hi = static_cast<int64_t>(s_tv[0] >> 64);
+    r.qmin = s_min[0];
+    r.qmax = s_max[0];
+    out[0] = r;
   }
 }
 
@@ -1231,11 +1278,28 @@ int64_t reduce_blocks(int64_t n) { return (n + RED_CELLS_PER_BLOCK - 1) / RED_CE
 
 hipError_t launch_reduce(int itype, const void* q, int64_t n, int periodic, ReducePartial* out,
                          hipStream_t s) {
-  const unsigned g = static_cast<unsigned>(reduce_blocks(n));
+  return launch_reduce_cpb(itype, q, n, periodic, RED_CELLS_PER_BLOCK, out, s);
+}
+
+int64_t reduce_min_cells_per_block() { return RED_CELLS_PER_BLOCK; }
+
+hipError_t launch_reduce_cpb(int itype, const void* q, int64_t n, int periodic, int64_t cpb,
+                             ReducePartial* out, hipStream_t s) {
+  if (cpb < 1) return hipErrorInvalidValue;
+  const unsigned g = static_cast<unsigned>((n + cpb - 1) / cpb);
   if (itype == FQNM_I32)
-    k_reduce<int32_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int32_t*>(q), n, periodic, out);
+    k_reduce<int32_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int32_t*>(q), n, periodic, cpb,
+                                                out);
   else
-    k_reduce<int64_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int64_t*>(q), n, periodic, out);
+    k_reduce<int64_t><<<g, RED_THREADS, 0, s>>>(static_cast<const int64_t*>(q), n, periodic, cpb,
+                                                out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const ReducePartial* in, int count, ReducePartial* out,
+                               hipStream_t s) {
+  if (count < 1) return hipErrorInvalidValue;
+  k_reduce_final<<<1, RED_THREADS, 0, s>>>(in, count, out);
   return hipGetLastError();
 }
 

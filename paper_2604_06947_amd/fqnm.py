@@ -46,7 +46,8 @@ def nd_tb_depth(steps_per_pass, rows=0):
 EXPORTED = [
     "fqnm_last_error", "fqnm_version", "fqnm_create", "fqnm_create_from_field",
     "fqnm_create_on_device", "fqnm_create_classical", "fqnm_step", "fqnm_get_state", "fqnm_state_device",
-    "fqnm_reconstruct", "fqnm_reconstruct_device", "fqnm_invariants_get", "fqnm_get_plan",
+    "fqnm_reconstruct", "fqnm_reconstruct_device", "fqnm_invariants_get",
+    "fqnm_invariants_get_noalloc", "fqnm_get_plan",
     "fqnm_set_plan", "fqnm_autotune", "fqnm_destroy", "fqnm_batch_create", "fqnm_batch_reset",
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
     "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
@@ -121,6 +122,7 @@ def lib():
             "fqnm_reconstruct": ([vp, vp], C.c_int),
             "fqnm_reconstruct_device": ([vp, vp], C.c_int),
             "fqnm_invariants_get": ([vp, C.POINTER(fqnm_invariants)], C.c_int),
+            "fqnm_invariants_get_noalloc": ([vp, C.POINTER(fqnm_invariants)], C.c_int),
             "fqnm_get_plan": ([vp, C.POINTER(fqnm_plan)], C.c_int),
             "fqnm_set_plan": ([vp, C.POINTER(fqnm_plan)], C.c_int),
             "fqnm_autotune": ([vp, i64], C.c_int),
@@ -279,15 +281,25 @@ def _i128(hi, lo):
     return (int(hi) << 64) + int(lo)
 
 
-def fqnm_invariants_get(h):
-    inv = fqnm_invariants()
-    _check(lib().fqnm_invariants_get(h, C.byref(inv)))
+def _invariants_dict(inv):
     k = inv.components
     return {"components": k, "steps_done": inv.steps_done,
             "sum": [_i128(inv.sum_hi[c], inv.sum_lo[c]) for c in range(k)],
             "min": [inv.qmin[c] for c in range(k)], "max": [inv.qmax[c] for c in range(k)],
             "tv": [_i128(inv.tv_hi[c], inv.tv_lo[c]) for c in range(k)],
             "ledger": [inv.ledger[c] for c in range(k)]}
+
+
+def fqnm_invariants_get(h):
+    inv = fqnm_invariants()
+    _check(lib().fqnm_invariants_get(h, C.byref(inv)))
+    return _invariants_dict(inv)
+
+
+def fqnm_invariants_get_noalloc(h):
+    inv = fqnm_invariants()
+    _check(lib().fqnm_invariants_get_noalloc(h, C.byref(inv)))
+    return _invariants_dict(inv)
 
 
 def fqnm_get_plan(h):
