@@ -162,6 +162,19 @@ fqnm_status validate_range(const fqnm_problem& p, int64_t lo, int64_t hi) {
   return FQNM_OK;
 }
 
+fqnm_status validate_drift(const fqnm_problem& p, int64_t lo, int64_t hi, int64_t steps) {
+  if (p.flux != FQNM_FLUX_LF_LINEAR && p.flux != FQNM_FLUX_LF_BURGERS) return FQNM_OK;
+  const int64_t lim = int64_t(1) << 52;
+  const int64_t d = steps > lim / 4 ? lim / 2 : 2 * steps;
+  const int64_t a = lo - d < -lim ? -lim : lo - d;
+  const int64_t b = hi + d > lim ? lim : hi + d;
+  fqnm_status st = validate_range(p, a, b);
+  if (st)
+    set_error("after these steps the Lax-Friedrichs states may leave the checked range (they can "
+              "move 2 counts per step past [min q0, max q0]): " + std::string(tl_error));
+  return st;
+}
+
 // d-D (Thm dimension_extension): the summed CFL number of the directions must
 // not exceed 1.  The composed quantised update has no exact maximum principle
 // (rounding steps of several directions can add up), so int32 states keep a
@@ -268,6 +281,28 @@ using namespace fqnm;
     }                                              \
   } while (0)
 
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Device memory of a context: carved from its block if it has one, else
+// allocated.
+static bool ctx_dmalloc(fqnm_ctx* ctx, void** p, size_t bytes) {
+  if (ctx->carve_base) {
+    const size_t off = round256(ctx->carve_used);
+    if (off + bytes > ctx->carve_size) return false;
+    *p = ctx->carve_base + off;
+    ctx->carve_used = off + bytes;
+    return true;
+  }
+  return hipMalloc(p, bytes) == hipSuccess;
+}
+
+static void ctx_dfree(fqnm_ctx* ctx, void* p) {
+  if (!p) return;
+  const char* c = static_cast<const char*>(p);
+  if (ctx->carve_base && c >= ctx->carve_base && c < ctx->carve_base + ctx->carve_size) return;
+  (void)hipFree(p);
+}
+
 static fqnm_status ctx_alloc(fqnm_ctx* ctx, void* borrowed) {
   const size_t bytes = ctx->state_bytes();
   if (borrowed) {
@@ -275,13 +310,15 @@ static fqnm_status ctx_alloc(fqnm_ctx* ctx, void* borrowed) {
       return fail(FQNM_ERR_ARG, "device state must be 16-byte aligned");
     ctx->buf[0] = borrowed;
     ctx->borrowed = true;
-  } else if (hipMalloc(&ctx->buf[0], bytes) != hipSuccess) {
-    return fail(FQNM_ERR_OOM, "hipMalloc of the state failed");
+  } else if (!ctx_dmalloc(ctx, &ctx->buf[0], bytes)) {
+    return fail(FQNM_ERR_OOM, "allocation of the state failed");
   }
-  if (hipMalloc(&ctx->buf[1], bytes) != hipSuccess)
-    return fail(FQNM_ERR_OOM, "hipMalloc of the second state buffer failed");
-  if (hipMalloc(&ctx->d_ledger, 3 * sizeof(long long)) != hipSuccess)
-    return fail(FQNM_ERR_OOM, "hipMalloc of the ledger failed");
+  if (!ctx_dmalloc(ctx, &ctx->buf[1], bytes))
+    return fail(FQNM_ERR_OOM, "allocation of the second state buffer failed");
+  void* led = nullptr;
+  if (!ctx_dmalloc(ctx, &led, 3 * sizeof(long long)))
+    return fail(FQNM_ERR_OOM, "allocation of the ledger failed");
+  ctx->d_ledger = static_cast<long long*>(led);
   CTX_HIP(hipMemsetAsync(ctx->d_ledger, 0, 3 * sizeof(long long), ctx->stream), "ledger reset");
   return FQNM_OK;
 }
@@ -289,22 +326,24 @@ static fqnm_status ctx_alloc(fqnm_ctx* ctx, void* borrowed) {
 static void ctx_free(fqnm_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream_sync_on_free) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->buf[0] && !ctx->borrowed) (void)hipFree(ctx->buf[0]);
-  if (ctx->buf[1]) (void)hipFree(ctx->buf[1]);
-  if (ctx->d_ledger) (void)hipFree(ctx->d_ledger);
-  if (ctx->d_lut) (void)hipFree(ctx->d_lut);
-  if (ctx->d_u) (void)hipFree(ctx->d_u);
-  if (ctx->d_red) (void)hipFree(ctx->d_red);
-  if (ctx->d_err) (void)hipFree(ctx->d_err);
-  if (ctx->d_ws) (void)hipFree(ctx->d_ws);
+  if (!ctx->borrowed) ctx_dfree(ctx, ctx->buf[0]);
+  ctx_dfree(ctx, ctx->buf[1]);
+  ctx_dfree(ctx, ctx->d_ledger);
+  ctx_dfree(ctx, ctx->d_lut);
+  ctx_dfree(ctx, ctx->d_u);
+  ctx_dfree(ctx, ctx->d_red);
+  ctx_dfree(ctx, ctx->d_err);
+  ctx_dfree(ctx, ctx->d_ws);
   delete ctx;
 }
 
 // Range of component 0 of the current state via the device reduction.
 fqnm_status fqnm::ctx_minmax(fqnm_ctx* ctx, int comp, int64_t* lo, int64_t* hi) {
   const int64_t nb = reduce_blocks(ctx->prob.n);
-  if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
-    return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
+  void* red = ctx->d_red;
+  if (!red && !ctx_dmalloc(ctx, &red, sizeof(ReducePartial) * nb))
+    return fail(FQNM_ERR_OOM, "allocation of reduction partials failed");
+  ctx->d_red = static_cast<ReducePartial*>(red);
   const char* q = static_cast<const char*>(ctx->buf[ctx->cur]) +
                   comp * ctx->prob.n * ctx->esize;
   CTX_HIP(launch_reduce(ctx->prob.itype, q, ctx->prob.n, 0, ctx->d_red, ctx->stream), "reduce");
@@ -340,6 +379,12 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     ctx->eparams.g1 = p.gamma - 1.0;
     ctx->eparams.fix = p.flux == FQNM_FLUX_EULER_ROE_EF || p.flux == FQNM_FLUX_EULER_ROE_EF_DENSITY;
     ctx->eparams.dens = dens;
+    void* flag = ctx->d_err;
+    if (!flag && !ctx_dmalloc(ctx, &flag, sizeof(int)))
+      return fail(FQNM_ERR_OOM, "allocation of the error flag failed");
+    ctx->d_err = static_cast<int*>(flag);
+    CTX_HIP(hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream), "flag reset");
+    ctx->eparams.err = ctx->d_err;
     return FQNM_OK;
   }
   int64_t lo, hi;
@@ -355,8 +400,8 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     const int64_t count = hi - lo + 1;
     if (count >= (int64_t(1) << 28)) return fail(FQNM_ERR_RANGE, "LUT range too large");
     const size_t eb = p.itype == FQNM_I32 ? 8 : 16;
-    if (hipMalloc(&ctx->d_lut, eb * count) != hipSuccess)
-      return fail(FQNM_ERR_OOM, "hipMalloc of the LUT failed");
+    if (!ctx_dmalloc(ctx, &ctx->d_lut, eb * count))
+      return fail(FQNM_ERR_OOM, "allocation of the LUT failed");
     CTX_HIP(launch_lut_build(p.itype, direct_split_policy(p), ctx->xp, ctx->d_lut, lo, count,
                              ctx->stream), "LUT build");
     ctx->xp.lut = ctx->d_lut;
@@ -497,6 +542,37 @@ fqnm_status fqnm_create_on_device(const fqnm_problem* prob, void* d_q, void* hip
   *out = ctx;
   return FQNM_OK;
 }
+
+}  // extern "C"
+
+size_t fqnm::ctx_carved_bytes(const fqnm_problem& p, int64_t lo, int64_t hi) {
+  const int comp = is_euler(p.flux) ? 3 : 1;
+  const size_t sb = round256(static_cast<size_t>(comp) * p.n * (p.itype == FQNM_I32 ? 4 : 8));
+  size_t b = 2 * sb + 256 + round256(sizeof(ReducePartial) * reduce_blocks(p.n));
+  if (p.eval == FQNM_EVAL_LUT && !is_euler(p.flux))
+    b += round256((p.itype == FQNM_I32 ? 8 : 16) * static_cast<size_t>(hi - lo + 1));
+  return b;
+}
+
+fqnm_status fqnm::ctx_create_carved(const fqnm_problem* prob, char* block, size_t bytes,
+                                    hipStream_t stream, fqnm_ctx** out) {
+  fqnm_ctx* ctx = nullptr;
+  fqnm_status st = ctx_new(prob, stream, out, &ctx);
+  if (st) return st;
+  if (!block || (reinterpret_cast<uintptr_t>(block) & 255) != 0) {
+    ctx_free(ctx);
+    return fail(FQNM_ERR_ARG, "block must be 256-byte aligned");
+  }
+  ctx->carve_base = block;
+  ctx->carve_size = bytes;
+  st = ctx_alloc(ctx, nullptr);  // buf[0] is carved first: the state already there
+  if (!st) st = ctx_finish(ctx);
+  if (st) { ctx_free(ctx); return st; }
+  *out = ctx;
+  return FQNM_OK;
+}
+
+extern "C" {
 
 fqnm_status fqnm_create_nd(const fqnm_problem* axes, int32_t dim, const void* q0_host,
                            void* hip_stream, fqnm_ctx** out) {
@@ -672,6 +748,11 @@ fqnm_status fqnm_step(fqnm_ctx* ctx, int64_t n_steps) {
   if (!ctx) return fail(FQNM_ERR_ARG, "ctx is NULL");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned by an earlier device error");
   if (n_steps < 0) return fail(FQNM_ERR_ARG, "n_steps must be >= 0");
+  if (ctx->range_error) return fail(FQNM_ERR_RANGE, "a density or pressure became non-positive");
+  if (!ctx->euler && !ctx->classical && ctx->dim == 1) {
+    fqnm_status st = validate_drift(ctx->prob, ctx->q0min, ctx->q0max, ctx->steps_done + n_steps);
+    if (st) return st;
+  }
   fqnm_status st = ctx_advance(ctx, n_steps, ctx->buf, &ctx->cur, ctx->plan);
   if (st) return st;
   ctx->steps_done += n_steps;
@@ -683,13 +764,34 @@ fqnm_status fqnm_step(fqnm_ctx* ctx, int64_t n_steps) {
   return FQNM_OK;
 }
 
+}  // extern "C"
+
+// Euler contexts: the kernels' sticky flag for a non-positive density or
+// pressure (the transfers of such a step are meaningless).  Once raised, the
+// context refuses every later call with FQNM_ERR_RANGE.
+fqnm_status fqnm::ctx_check_flag(fqnm_ctx* ctx) {
+  if (ctx->range_error) return fail(FQNM_ERR_RANGE, "a density or pressure became non-positive");
+  if (!ctx->euler || !ctx->d_err) return FQNM_OK;
+  int h = 0;
+  CTX_HIP(hipMemcpyAsync(&h, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+          "copy flag");
+  CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+  if (h) {
+    ctx->range_error = true;
+    return fail(FQNM_ERR_RANGE, "a density or pressure became non-positive");
+  }
+  return FQNM_OK;
+}
+
+extern "C" {
+
 fqnm_status fqnm_get_state(fqnm_ctx* ctx, void* q_host) {
   if (!ctx || !q_host) return fail(FQNM_ERR_ARG, "NULL argument");
   if (ctx->poisoned) return fail(FQNM_ERR_DEVICE, "context is poisoned");
   CTX_HIP(hipMemcpyAsync(q_host, ctx->buf[ctx->cur], ctx->state_bytes(), hipMemcpyDeviceToHost,
                          ctx->stream), "copy state");
   CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
-  return FQNM_OK;
+  return ctx_check_flag(ctx);
 }
 
 fqnm_status fqnm_state_device(fqnm_ctx* ctx, void** d_q) {
@@ -731,7 +833,7 @@ fqnm_status fqnm_reconstruct(fqnm_ctx* ctx, double* u_host) {
   CTX_HIP(hipMemcpyAsync(u_host, ctx->d_u, sizeof(double) * total, hipMemcpyDeviceToHost,
                          ctx->stream), "copy field");
   CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
-  return FQNM_OK;
+  return ctx_check_flag(ctx);
 }
 
 fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
@@ -744,8 +846,10 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
   out->steps_done = ctx->steps_done;
   const int64_t n = ctx->prob.n;
   const int64_t nb = reduce_blocks(n);
-  if (!ctx->d_red && hipMalloc(&ctx->d_red, sizeof(ReducePartial) * nb) != hipSuccess)
-    return fail(FQNM_ERR_OOM, "hipMalloc of reduction partials failed");
+  void* red = ctx->d_red;
+  if (!red && !ctx_dmalloc(ctx, &red, sizeof(ReducePartial) * nb))
+    return fail(FQNM_ERR_OOM, "allocation of reduction partials failed");
+  ctx->d_red = static_cast<ReducePartial*>(red);
   std::vector<ReducePartial> h(nb);
   for (int c = 0; c < ncomp; ++c) {
     const char* q = static_cast<const char*>(ctx->buf[ctx->cur]) + c * n * ctx->esize;
@@ -775,7 +879,7 @@ fqnm_status fqnm_invariants_get(fqnm_ctx* ctx, fqnm_invariants* out) {
           "copy ledger");
   CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
   for (int c = 0; c < 3; ++c) out->ledger[c] = c < ncomp ? led[c] : 0;
-  return FQNM_OK;
+  return ctx_check_flag(ctx);
 }
 
 fqnm_status fqnm_quantise(const double* u_host, int64_t n, double delta, int32_t itype,

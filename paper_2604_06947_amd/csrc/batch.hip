@@ -435,6 +435,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       hi = std::max(hi, v);
     }
     st = validate_range(p, lo, hi);
+    if (!st) st = validate_drift(p, lo, hi, steps[k]);
     if (st) { batch_free(b); return st; }
     const int64_t per16 = 16 / esize_of(p);
     b->off.push_back(b->total);

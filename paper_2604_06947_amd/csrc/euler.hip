@@ -105,7 +105,9 @@ __device__ __forceinline__ double acoustic_fix(double l, double e, double lLk, d
 
 // Roe flux of two cells, then the three quantised transfers (density-only:
 // the density transfer and the FP64 fluxes of m and E as bit patterns).
-__device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L, const Prim& R,
+// Returns false when a value to be rounded is not a number or too large for
+// the conversion (|v| >= 2^51), i.e. when the transfer is meaningless.
+__device__ __forceinline__ bool roe_transfer(const EulerParams& E, const Prim& L, const Prim& R,
                                              int64_t T[3]) {
   const double w = L.s + R.s;
   double ub = L.s * L.u;
@@ -166,6 +168,7 @@ __device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L
   const double fl[3] = {L.f0, L.f1, L.f2};
   const double fr[3] = {R.f0, R.f1, R.f2};
   const double D[3] = {D0, D1, D2};
+  bool ok = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double F = fl[c] + fr[c];
@@ -177,9 +180,11 @@ __device__ __forceinline__ void roe_transfer(const EulerParams& E, const Prim& L
     } else {
       double v = F * E.lambda;
       v = v / E.delta;
-      T[c] = round_to<int64_t>(v);  // |v| < 2^51: counts are validated below 2^51
+      ok = ok && fabs(v) < 2251799813685248.0;  // false for NaN
+      T[c] = round_to<int64_t>(v);  // exact for |v| < 2^51
     }
   }
+  return ok;
 }
 
 __device__ __forceinline__ int64_t ghost(int64_t g, int64_t n, int bc) {
@@ -204,11 +209,23 @@ __device__ __forceinline__ void euler_tile_step(const int64_t* __restrict__ src,
   const bool ghosts = outflow && (b0 - EKS < 0 || b0 - EKS + EB > n);
   const int nled = E.dens ? 1 : 3;  // density-only: only the counts have a ledger
   for (int s = 0; s < nst; ++s) {
-    s_prim[t] = cell_primitives(E, qr, qm, qE);
+    const Prim pc = cell_primitives(E, qr, qm, qE);
+    s_prim[t] = pc;
+    // positions [s, EB-1-s] hold the exact state after s steps; a cell of the
+    // domain there whose density or pressure is not positive (or NaN) makes
+    // the flux meaningless: raise the context's sticky flag
+    if (E.err && t >= s && t <= EB - 1 - s && g >= 0 && g < n && !(pc.r > 0.0 && pc.p > 0.0))
+      __hip_atomic_store(E.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // interface between positions t and t+1 (t < EB-1)
     int64_t T[3] = {0, 0, 0};
-    if (t < EB - 1) roe_transfer(E, s_prim[t], s_prim[t + 1], T);
+    if (t < EB - 1) {
+      const bool ok = roe_transfer(E, s_prim[t], s_prim[t + 1], T);
+      // an interface between two exact positions with a cell of the domain
+      // on one side (the outflow boundary faces included)
+      if (!ok && E.err && t >= s && t + 1 <= EB - 1 - s && g + 1 >= 0 && g < n)
+        __hip_atomic_store(E.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     s_T[0][t] = T[0];
     s_T[1][t] = T[1];
     s_T[2][t] = T[2];

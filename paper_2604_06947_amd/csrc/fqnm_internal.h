@@ -111,6 +111,8 @@ struct EulerParams {
   double g1;  // gamma - 1
   int fix;    // entropy fix on the acoustic waves
   int dens;   // density-only: components 1, 2 hold FP64 m and E (bit patterns)
+  int* err;   // set to 1 when a cell's density or pressure is not positive
+              // (or not a number) at the start of a step; sticky, may be null
 };
 // nsteps (1 .. euler_steps_per_launch()) steps in one launch.
 hipError_t launch_euler_step(const int64_t* src, int64_t* dst, int64_t n, int bc,

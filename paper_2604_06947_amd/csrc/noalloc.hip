@@ -140,5 +140,5 @@ extern "C" fqnm_status fqnm_invariants_get_noalloc(fqnm_ctx* ctx, fqnm_invariant
     out->qmax[c] = rec[c].qmax;
     out->ledger[c] = led[c];
   }
-  return FQNM_OK;
+  return ctx_check_flag(ctx);
 }

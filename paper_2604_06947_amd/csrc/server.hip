@@ -106,6 +106,7 @@ struct SReq {
   fqnm_ctx* ctx = nullptr;
   int64_t tick_steps = 0;
   bool holds_arena = false;
+  int64_t lo = 0, hi = 0;  // range of the initial state (component 0)
 };
 
 // Device bytes a request holds while admitted.  The layout inside the block
@@ -116,11 +117,15 @@ size_t state_bytes_rounded(const fqnm_problem& p, size_t es, int comp) {
   return (sb + 255) / 256 * 256;
 }
 
-size_t footprint(const fqnm_problem& p, int path, size_t es, int comp) {
+// Single-grid requests (R_SINGLE) get their whole context -- both state
+// buffers, ledger, reduction partials and, in table mode, the table over the
+// initial range -- carved from their arena block, so the budget bounds all of
+// the device memory the server's requests hold.
+size_t footprint(const fqnm_problem& p, int path, size_t es, int comp, int64_t lo, int64_t hi) {
   const size_t n = static_cast<size_t>(p.n);
   if (path == R_RESIDENT) return (n + 4) * es;                           // in place + guard cells
   if (path == R_EULER) return 2 * state_bytes_rounded(p, es, comp) + 256;  // ping-pong + ledger
-  return 2 * comp * n * es + 64 * 1024;  // state + the single-grid stepper's own buffers
+  return ctx_carved_bytes(p, lo, hi);
 }
 
 }  // namespace
@@ -174,9 +179,10 @@ void fail_all(fqnm_server* s, const char* what, hipError_t e) {
   s->err = std::string(what) + ": " + hipGetErrorString(e);
 }
 
-// Zero a request's ledger with a tiny kernel (kept off memset nodes).
+// Zero a request's ledger and its range flag (the word after the ledger)
+// with a tiny kernel (kept off memset nodes).
 __global__ void k_zero3(long long* p) {
-  if (threadIdx.x < 3) p[threadIdx.x] = 0;
+  if (threadIdx.x < 4) p[threadIdx.x] = 0;
 }
 
 // Reserve arena space (worker thread only; cheap host bookkeeping).
@@ -204,7 +210,7 @@ void upload(fqnm_server* s, SReq* r) {
     e = hipGetLastError();
   }
   if (e == hipSuccess && r->path == R_SINGLE) {
-    fqnm_status st = fqnm_create_on_device(&r->prob, base, s->stream, &r->ctx);
+    fqnm_status st = ctx_create_carved(&r->prob, base, r->bytes, s->stream, &r->ctx);
     if (st) r->status = st;  // completes at once with this status
   }
   if (e != hipSuccess) {
@@ -225,11 +231,16 @@ void retire(fqnm_server* s, SReq* r) {
       if (st) r->status = st;
     } else {
       const char* src = r->path == R_EULER ? r->buf[r->parity] : r->buf[0];
+      int flag = 0;
       e = hipMemcpyAsync(r->out, src, sb, hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess && r->path == R_EULER)
+        e = hipMemcpyAsync(&flag, r->ledger + 3, sizeof(int), hipMemcpyDeviceToHost, s->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) {
         fail_all(s, "retire", e);
         r->status = FQNM_ERR_DEVICE;
+      } else if (flag) {
+        r->status = FQNM_ERR_RANGE;  // a density or pressure became non-positive
       }
     }
   }
@@ -282,6 +293,7 @@ bool run_tick(fqnm_server* s) {
       R.E.fix = r->prob.flux == FQNM_FLUX_EULER_ROE_EF ||
                 r->prob.flux == FQNM_FLUX_EULER_ROE_EF_DENSITY;
       R.E.dens = is_euler_density(r->prob.flux);
+      R.E.err = reinterpret_cast<int*>(r->ledger + 3);
       const int32_t id = static_cast<int32_t>(er.size());
       er.push_back(R);
       const int64_t nt = euler_tiles(r->prob.n);
@@ -499,6 +511,11 @@ fqnm_status fqnm_server_submit(fqnm_server* s, const fqnm_problem* prob, const v
     }
     st = validate_range(*prob, lo, hi);
     if (!st && r->comp == 3 && c == 0 && lo <= 0) st = fail(FQNM_ERR_RANGE, "density must be > 0");
+    if (!st && r->comp == 1) st = validate_drift(*prob, lo, hi, n_steps);
+    if (c == 0) {
+      r->lo = lo;
+      r->hi = hi;
+    }
   }
   if (st) { delete r; return st; }
   r->steps = n_steps;
@@ -506,7 +523,11 @@ fqnm_status fqnm_server_submit(fqnm_server* s, const fqnm_problem* prob, const v
   r->pol = policy_of(*prob, false);
   r->path = r->comp == 3 ? R_EULER
                          : (resident_eligible(*prob, r->pol, n_steps) ? R_RESIDENT : R_SINGLE);
-  r->bytes = footprint(*prob, r->path, r->es, r->comp);
+  if (r->path == R_SINGLE && prob->eval == FQNM_EVAL_LUT && r->hi - r->lo + 1 >= (int64_t(1) << 28)) {
+    delete r;
+    return fail(FQNM_ERR_RANGE, "LUT range too large");
+  }
+  r->bytes = footprint(*prob, r->path, r->es, r->comp, r->lo, r->hi);
   if (r->bytes > s->budget) {
     delete r;
     return fail(FQNM_ERR_OOM, "request footprint exceeds the server budget");

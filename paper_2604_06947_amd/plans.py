@@ -10,18 +10,26 @@ BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
 # the one-step-per-pass streaming plan reported beside it
 STREAM_PLAN_W3 = (KERNEL_STREAM, 4, 1)
 
-# HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by a plain device copy of known size (see profiles/).
-# Valid only for the kernel sources they were measured on: the benchmark
-# reports null when the hash of those sources differs.
+# Counter results of the timed kernels (rocprofv3 runs recorded under
+# profiles/), per launch of the benchmark's plan: HBM traffic (FETCH_SIZE and
+# WRITE_SIZE scaled by a plain device copy of known size), VALU
+# wavefront-instructions (SQ_INSTS_VALU) and the share of LDS-active cycles
+# lost to bank conflicts.  Valid only for the kernel sources they were
+# measured on: the benchmark reports null when the hash of those sources
+# (first 16 hex digits of SHA-256 over the files in order) differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
-MEASURED_SOURCES_SHA = "cce23d36ccc8e6ea"
-TRAFFIC_BYTES_PER_LAUNCH = {
-    "w2": 11415 * 1024,  # k_tblock<int, P_LUT, 4>, 40 steps per launch
-    "w6": 153359 * 1024,  # k_nd_tb<int, P_EO, 2, 4, true>, 24 rows per wavefront, 4 steps
-}
 ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
-ND_MEASURED_SOURCES_SHA = "beac81b3b4612721"
+EULER_KERNEL_SOURCES = ("csrc/euler.hip", "csrc/fqnm_device.h")
+COUNTERS = {
+    "w2": {"sources": KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
+           "valu_insts": None, "lds_bank_conflict_frac": None},
+    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
+                  "valu_insts": None, "lds_bank_conflict_frac": None},
+    "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
+           "valu_insts": None, "lds_bank_conflict_frac": None},
+    "euler_multi": {"sources": EULER_KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
+                    "valu_insts": None, "lds_bank_conflict_frac": None},
+}
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery
 TWIN_PLAN_W2 = (KERNEL_TBLOCK, 4, 24)
