@@ -148,7 +148,14 @@ typedef struct {
  * temporal blocking (2-D grids; vec 2 or 4 for int32, 2 for int64, dividing
  * the length of axis 0): `depth & 0xFF` steps per pass (1, 2, 4 or 8; a
  * remainder runs as smaller passes) and `depth >> 8` cells marched along
- * axis 1 per wavefront (0 = chosen from the grid size).  d-D contexts run
+ * axis 1 per wavefront (0 = chosen from the grid size); 10 = kernel 1's
+ * tiles (vec 4 or 8, `depth` steps per pass) with every pass in one
+ * cooperative launch: each wavefront keeps its tile in registers between
+ * passes and swaps its edge cells with its two neighbours through memory,
+ * every wait bounded (a launch that times out makes the next syncing call
+ * return FQNM_ERR_DEVICE); int32 states on periodic grids, UPWIND or
+ * BURGERS_EO maps (table or direct), and only when every workgroup of the
+ * launch can be resident at once (fqnm_set_plan checks).  d-D contexts run
  * kernels 6 and 9 only.  Zero fields mean "keep" (on a change between
  * kernels 6 and 9: that kernel's default, vec 4 (int64: 2) and 16 rows, or
  * vec 2 and 4 steps per pass). */

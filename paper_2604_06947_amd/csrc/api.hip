@@ -334,7 +334,47 @@ static void ctx_free(fqnm_ctx* ctx) {
   ctx_dfree(ctx, ctx->d_red);
   ctx_dfree(ctx, ctx->d_err);
   ctx_dfree(ctx, ctx->d_ws);
+  ctx_dfree(ctx, ctx->d_exch);
+  ctx_dfree(ctx, ctx->d_perr);
   delete ctx;
+}
+
+// Exchange buffer and error flag of the persistent plan, grown on demand
+// (zeroed: every word carries tag 0, below any pass tag).
+static fqnm_status ctx_persist_buffers(fqnm_ctx* ctx, int vec, int depth) {
+  int khalo = 0;
+  int64_t ntiles = 0;
+  if (!persist_geometry(ctx->prob.n, vec, depth, &khalo, &ntiles))
+    return fail(FQNM_ERR_ARG, "the grid cannot be tiled for this persistent plan");
+  const size_t need = sizeof(uint64_t) * 4 * static_cast<size_t>(ntiles) * khalo;
+  if (!ctx->d_perr) {
+    void* p = nullptr;
+    if (!ctx_dmalloc(ctx, &p, sizeof(int))) return fail(FQNM_ERR_OOM, "allocation failed");
+    ctx->d_perr = static_cast<int*>(p);
+    CTX_HIP(hipMemsetAsync(ctx->d_perr, 0, sizeof(int), ctx->stream), "flag reset");
+  }
+  if (ctx->exch_bytes < need) {
+    ctx_dfree(ctx, ctx->d_exch);
+    ctx->d_exch = nullptr;
+    ctx->exch_bytes = 0;
+    void* p = nullptr;
+    if (!ctx_dmalloc(ctx, &p, need)) return fail(FQNM_ERR_OOM, "allocation of the exchange buffer failed");
+    ctx->d_exch = static_cast<uint64_t*>(p);
+    ctx->exch_bytes = need;
+    ctx->exch_tag = 0;
+    CTX_HIP(hipMemsetAsync(ctx->d_exch, 0, need, ctx->stream), "exchange reset");
+  }
+  return FQNM_OK;
+}
+
+static bool persist_plan_ok(fqnm_ctx* ctx, const fqnm_plan& pl) {
+  int khalo = 0;
+  int64_t ntiles = 0;
+  if (ctx->classical || ctx->euler || ctx->dim > 1) return false;
+  if (!persist_available(ctx->prob.itype, ctx->pol, pl.vec, ctx->prob.bc)) return false;
+  if (!persist_geometry(ctx->prob.n, pl.vec, pl.depth, &khalo, &ntiles)) return false;
+  bool fits = false;
+  return persist_fits(ctx->pol, pl.vec, ntiles, &fits) == hipSuccess && fits;
 }
 
 // Range of component 0 of the current state via the device reduction.
@@ -718,6 +758,22 @@ fqnm_status fqnm::ctx_advance(fqnm_ctx* ctx, int64_t n_steps, void* const buf[2]
       k = std::min<int64_t>(euler_steps_per_launch(), left);
       e = launch_euler_step(static_cast<const int64_t*>(src), static_cast<int64_t*>(dst), p.n,
                             p.bc, ctx->eparams, static_cast<int>(k), ctx->d_ledger, ctx->stream);
+    } else if (pl.kernel == K_TBLOCK_PERSIST) {
+      // every pass in one cooperative launch
+      k = left;
+      fqnm_status st = ctx_persist_buffers(ctx, pl.vec, pl.depth);
+      if (st) return st;
+      const int64_t passes = (k + pl.depth - 1) / pl.depth;
+      if (k > INT32_MAX || passes >= (int64_t(1) << 30))
+        return fail(FQNM_ERR_ARG, "too many steps for one persistent launch");
+      if (static_cast<uint64_t>(ctx->exch_tag) + passes >= (uint64_t(1) << 32)) {
+        CTX_HIP(hipMemsetAsync(ctx->d_exch, 0, ctx->exch_bytes, ctx->stream), "exchange reset");
+        ctx->exch_tag = 0;
+      }
+      e = launch_persist(ctx->pol, pl.vec, static_cast<const int32_t*>(src),
+                         static_cast<int32_t*>(dst), p.n, static_cast<int>(k), pl.depth, ctx->xp,
+                         ctx->d_exch, ctx->exch_tag, ctx->d_perr, 1 << 20, ctx->stream);
+      ctx->exch_tag += static_cast<uint32_t>(passes);
     } else if (pl.kernel == K_TBLOCK_WG4 || pl.kernel == K_TBLOCK_WG8) {
       k = std::min<int64_t>(pl.depth, left);
       e = launch_tblock_wg(pl.kernel == K_TBLOCK_WG4 ? 4 : 8, pl.vec,
@@ -771,6 +827,16 @@ fqnm_status fqnm_step(fqnm_ctx* ctx, int64_t n_steps) {
 // context refuses every later call with FQNM_ERR_RANGE.
 fqnm_status fqnm::ctx_check_flag(fqnm_ctx* ctx) {
   if (ctx->range_error) return fail(FQNM_ERR_RANGE, "a density or pressure became non-positive");
+  if (ctx->d_perr) {
+    int h = 0;
+    CTX_HIP(hipMemcpyAsync(&h, ctx->d_perr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+            "copy flag");
+    CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
+    if (h) {
+      ctx->poisoned = true;
+      return fail(FQNM_ERR_DEVICE, "a persistent launch timed out waiting for a neighbouring tile");
+    }
+  }
   if (!ctx->euler || !ctx->d_err) return FQNM_OK;
   int h = 0;
   CTX_HIP(hipMemcpyAsync(&h, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
@@ -952,11 +1018,22 @@ fqnm_status fqnm_set_plan(fqnm_ctx* ctx, const fqnm_plan* plan) {
     return FQNM_OK;
   }
   if ((plan->kernel >= K_STREAM && plan->kernel <= K_TBLOCK_B8) ||
-      plan->kernel == K_TBLOCK_WG4 || plan->kernel == K_TBLOCK_WG8)
+      plan->kernel == K_TBLOCK_WG4 || plan->kernel == K_TBLOCK_WG8 ||
+      plan->kernel == K_TBLOCK_PERSIST)
     pl.kernel = plan->kernel;
   else if (plan->kernel != 0) return fail(FQNM_ERR_ARG, "unknown kernel");
   if (plan->vec) pl.vec = plan->vec;
   if (plan->depth) pl.depth = plan->depth;
+  if (pl.kernel == K_TBLOCK_PERSIST) {
+    if (!persist_plan_ok(ctx, pl))
+      return fail(FQNM_ERR_ARG, "the persistent plan needs int32 states on a periodic grid, a "
+                                "table or direct split kind, vec 4 or 8, tiles of at least depth "
+                                "cells and a grid that is resident at once");
+    fqnm_status st = ctx_persist_buffers(ctx, pl.vec, pl.depth);
+    if (st) return st;
+    ctx->plan = pl;
+    return FQNM_OK;
+  }
   if (pl.kernel == K_TBLOCK_WG4 || pl.kernel == K_TBLOCK_WG8) {
     if (ctx->classical || ctx->prob.itype != FQNM_I32 || ctx->pol != P_LUT ||
         ctx->prob.bc != FQNM_BC_PERIODIC)
@@ -1036,6 +1113,10 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
         if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK_IL, v, d, 0});
       }
     }
+    for (int d : {16, 24, 32, 40}) {
+      const fqnm_plan pp{K_TBLOCK_PERSIST, v, d, 0};
+      if (persist_plan_ok(ctx, pp)) cand.push_back(pp);
+    }
   }
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
@@ -1049,13 +1130,19 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
         hipSuccess) { st = fail(FQNM_ERR_DEVICE, "autotune copy"); break; }
     st = ctx_advance(ctx, std::min<int64_t>(steps_per_trial, 4 * c.depth), sb, &cur, c);  // warm
     if (st) break;
-    (void)hipEventRecord(e0, ctx->stream);
-    st = ctx_advance(ctx, steps_per_trial, sb, &cur, c);
+    // the better of two timed trials, so that one noisy trial does not pick the plan
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2 && !st; ++rep) {
+      (void)hipEventRecord(e0, ctx->stream);
+      st = ctx_advance(ctx, steps_per_trial, sb, &cur, c);
+      if (st) break;
+      (void)hipEventRecord(e1, ctx->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(FQNM_ERR_DEVICE, "autotune sync"); break; }
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      ms = t < ms ? t : ms;
+    }
     if (st) break;
-    (void)hipEventRecord(e1, ctx->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(FQNM_ERR_DEVICE, "autotune sync"); break; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
     if (ms < best) { best = ms; bestp = c; }
   }
   (void)hipEventDestroy(e0);

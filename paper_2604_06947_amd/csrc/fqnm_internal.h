@@ -22,7 +22,8 @@ enum : int {
   K_ND_MARCH = 6,  // d-D grids: strips along axis 0 marching along the last axis
   K_TBLOCK_WG4 = 7,  // workgroup tiles of 4 or 8 wavefronts with overlapping windows
   K_TBLOCK_WG8 = 8,  // (int32 tables, periodic grids)
-  K_ND_TB = 9        // 2-D grids: several steps per pass
+  K_ND_TB = 9,       // 2-D grids: several steps per pass
+  K_TBLOCK_PERSIST = 10  // every pass of a temporally blocked plan in one cooperative launch
 };
 
 // Per-block partial results of the reduction kernel (one record per block).
@@ -50,6 +51,20 @@ int scalar_tile_positions(int kernel, int vec);     // cells loaded per tile
 bool tblock_wg_valid(int nw, int vec, int ksteps);
 hipError_t launch_tblock_wg(int nw, int vec, const int32_t* src, int32_t* dst, int64_t n,
                             int ksteps, const XParams& P, hipStream_t s);
+
+// Persistent temporal blocking (K_TBLOCK_PERSIST): int32 states on periodic
+// grids, table or direct split policies, vec 4 or 8.  persist_geometry gives
+// the halo and the tile count of a plan (false if the grid cannot be tiled
+// with at least khalo cells per tile); persist_fits whether the cooperative
+// grid can be resident at once; the exchange buffer holds
+// 2 * 2 * ntiles * khalo 64-bit words, zero or holding tags below tag0 + 1;
+// one launch advances nsteps steps, tags tag0 + 1 .. tag0 + passes - 1.
+bool persist_available(int itype, int pol, int vec, int bc);
+bool persist_geometry(int64_t n, int vec, int depth, int* khalo, int64_t* ntiles);
+hipError_t persist_fits(int pol, int vec, int64_t ntiles, bool* fits);
+hipError_t launch_persist(int pol, int vec, const int32_t* src, int32_t* dst, int64_t n,
+                          int nsteps, int depth, const XParams& P, uint64_t* exch, uint32_t tag0,
+                          int* err, int spin, hipStream_t s);
 
 // FP64 split finite-volume twin (state u in doubles).
 bool classical_variant_available(int pol, int kernel, int vec);

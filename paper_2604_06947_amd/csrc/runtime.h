@@ -41,6 +41,12 @@ struct fqnm_ctx {
   size_t carve_size = 0, carve_used = 0;
   size_t ws_bytes = 0;
   int dim = 1;           // > 1: d-dimensional grid, prob.n = total cells, axes in nd
+  // persistent plan (K_TBLOCK_PERSIST): halo exchange words, the next pass
+  // tag, and the flag a launch raises when a neighbour wait times out
+  uint64_t* d_exch = nullptr;
+  size_t exch_bytes = 0;
+  uint32_t exch_tag = 0;
+  int* d_perr = nullptr;
   fqnm::NdParams nd{};
 
   size_t state_bytes() const { return static_cast<size_t>(comp) * prob.n * esize; }

@@ -444,6 +444,215 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
 }
 
 // ---------------------------------------------------------------------------
+// K10: persistent temporal blocking on periodic grids.  One launch runs every
+// pass of a k_tblock-style plan (64*V positions per wavefront, `depth` steps
+// per pass, a halo of `khalo` >= depth cells on each side), but a wavefront
+// keeps its tile in registers from one pass to the next instead of storing
+// it and ending the launch: between passes it hands the `khalo` cells at each
+// end of its tile to its two neighbouring tiles through memory and takes
+// theirs as its new halo.  Each exchanged cell is one 64-bit word holding the
+// value and the pass it belongs to, written and read with relaxed
+// device-scope atomics: the tag alone tells a reader that a word is the one
+// it waits for, so no other ordering between the words is needed.  Two
+// buffers alternate by pass parity; a tile can only overwrite a buffer again
+// after both neighbours have read it (they need this tile's next exchange
+// before they can produce theirs).
+//
+// Tiles: tile t holds the cells [s(t), s(t+1)), s(t) = floor(t*n/ntiles)
+// rounded down to a multiple of V (s(ntiles) = n); the host checks that every
+// tile holds between khalo and 64*V - 2*khalo cells.  At the start of a pass
+// the window positions [0, 2*khalo + T) hold exact states (halo refreshed,
+// tile interior carried over); the positions behind them are never read by
+// the valid region and are reset to an in-range state.
+//
+// The launch is cooperative (every workgroup resident at once, checked by the
+// host and by the runtime), and every wait is bounded: a wavefront that polls
+// more than `spin` times raises the error flag, and every waiting wavefront
+// leaves once it sees the flag, so the launch always ends; the host reports
+// FQNM_ERR_DEVICE.  Int32 states, split or two-point policies, and table
+// slices in LDS as in K2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t persist_tile_start(int64_t t, int64_t n, int64_t ntiles,
+                                                      int V) {
+  if (t >= ntiles) return n;
+  const int64_t s = t * (n / ntiles) + (t * (n % ntiles)) / ntiles;
+  return s & ~static_cast<int64_t>(V - 1);
+}
+
+__device__ __forceinline__ uint64_t persist_pack(int32_t v, uint32_t tag) {
+  return (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(v);
+}
+
+template <int POL, int V>
+__global__ __launch_bounds__(256) void k_persist(const int32_t* __restrict__ src,
+                                                 int32_t* __restrict__ dst, int64_t n,
+                                                 int nsteps, int depth, int khalo, int ntiles,
+                                                 XParams P, uint64_t* __restrict__ exch,
+                                                 uint32_t tag0, int* __restrict__ err, int spin) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= ntiles) return;  // the whole wavefront leaves together
+  const int64_t s0 = persist_tile_start(tile, n, ntiles, V);
+  const int T = static_cast<int>(persist_tile_start(tile + 1, n, ntiles, V) - s0);
+  const int64_t w = s0 - khalo;
+  const int off0 = lane * V;
+  int32_t q[V];
+  if (w >= 0 && w + 64 * V <= n) {
+    load_vec<int32_t, V>(src + w + off0, q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) q[j] = src[wrap_index(w + off0 + j, n)];
+  }
+  const LutView L = lut_view(P);
+  const int lim = 2 * khalo + T;  // exact positions at the start of a pass
+  const int64_t left = tile > 0 ? tile - 1 : ntiles - 1;
+  const int64_t right = tile + 1 < ntiles ? tile + 1 : 0;
+  __shared__ int2 s_win[4][TB_WIN];
+  int32_t slo = 1, shi = 0;  // range of the staged table slice (empty)
+  long long led = 0;
+  bool failed = false;
+  int done = 0;
+  uint32_t pass = 0;
+  while (done < nsteps) {
+    const int ks = nsteps - done < depth ? nsteps - done : depth;
+    // range of the exact positions; the ones behind take an in-range state
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      if (off0 + j < lim) {
+        mn = q[j] < mn ? q[j] : mn;
+        mx = q[j] > mx ? q[j] : mx;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int32_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (off0 + j >= lim) q[j] = mn;
+    bool stepped = false;
+    if constexpr (POL == P_LUT) {
+      const int64_t span = static_cast<int64_t>(mx) - mn;
+      if (span < TB_WIN) {  // wavefront-uniform
+        int2* win = s_win[wave];
+        if (mn < slo || mx > shi) {
+          // restage: the slice of TB_WIN entries centred on the tile's range
+          // (clamped to the table), so that later passes can reuse it
+          int64_t lo = static_cast<int64_t>(mn) - (TB_WIN - 1 - span) / 2;
+          const int64_t tlo = P.lut_lo, thi = P.lut_lo + P.lut_last;
+          if (lo + TB_WIN - 1 > thi) lo = thi - (TB_WIN - 1);
+          if (lo < tlo) lo = tlo;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          for (int i = lane; i < TB_WIN; i += 64) {
+            const uint32_t off = (static_cast<uint32_t>(lo) + static_cast<uint32_t>(i) -
+                                  static_cast<uint32_t>(P.lut_lo)) << 3;
+            const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
+            win[i] = make_int2(e[0], e[1]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          slo = static_cast<int32_t>(lo);
+          shi = static_cast<int32_t>(lo + TB_WIN - 1);
+        }
+        const uint32_t base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(win)));
+        const uint32_t end = base + (static_cast<uint32_t>(shi - slo) << 3);
+        uint32_t a[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(slo)) << 3);
+        for (int s = 0; s < ks; ++s) tb_step_addr<V>(a, end);
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          q[j] = static_cast<int32_t>(static_cast<uint32_t>(slo) +
+                                      static_cast<uint32_t>(static_cast<int32_t>(a[j] - base) >> 3));
+        stepped = true;
+      }
+    }
+    if (!stepped) {
+      if constexpr (POL == P_LUT) {
+        switch (P.lut_pol) {
+          case P_UPWIND_POS:
+            tb_steps_direct<int32_t, P_UPWIND_POS, V>(P, L, q, w + off0, n, true, false, ks, led);
+            break;
+          case P_UPWIND_NEG:
+            tb_steps_direct<int32_t, P_UPWIND_NEG, V>(P, L, q, w + off0, n, true, false, ks, led);
+            break;
+          default:
+            tb_steps_direct<int32_t, P_EO, V>(P, L, q, w + off0, n, true, false, ks, led);
+            break;
+        }
+      } else {
+        tb_steps_direct<int32_t, POL, V>(P, L, q, w + off0, n, true, false, ks, led);
+      }
+    }
+    done += ks;
+    ++pass;
+    if (done >= nsteps) break;
+    // hand the first and last khalo cells of the tile to the neighbours and
+    // take their cells as the new halo
+    const uint32_t tag = tag0 + pass;
+    const int64_t par = pass & 1;
+    uint64_t* mine = exch + (par * ntiles + tile) * 2 * khalo;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int o = off0 + j;
+      if (o >= khalo && o < 2 * khalo)
+        __hip_atomic_store(mine + (o - khalo), persist_pack(q[j], tag), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      if (o >= T && o < T + khalo)
+        __hip_atomic_store(mine + khalo + (o - T), persist_pack(q[j], tag), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t* from_left = exch + ((par * ntiles + left) * 2 + 1) * khalo;
+    const uint64_t* from_right = exch + (par * ntiles + right) * 2 * khalo;
+    uint32_t need = 0;  // bit j: cell j still waits for its word
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int o = off0 + j;
+      if (o < khalo || (o >= khalo + T && o < lim)) need |= 1u << j;
+    }
+    for (int it = 0;; ++it) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        if (need & (1u << j)) {
+          const int o = off0 + j;
+          const uint64_t* p = o < khalo ? from_left + o : from_right + (o - khalo - T);
+          const uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (static_cast<uint32_t>(v >> 32) == tag) {
+            q[j] = static_cast<int32_t>(static_cast<uint32_t>(v));
+            need &= ~(1u << j);
+          }
+        }
+      }
+      if (!__any(need != 0)) break;
+      if ((it & 63) == 63) {
+        const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e != 0 || it >= spin) {
+          if (e == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          failed = true;
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (failed) break;  // wavefront-uniform
+  }
+  if (failed) return;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int o = off0 + j;
+    if (o >= khalo && o < khalo + T) dst[s0 + (o - khalo)] = q[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K5: workgroup tiles with overlapping wavefront windows (int32 tables,
 // periodic grids).  The NW wavefronts of a workgroup hold windows of 64*V
 // cells that overlap their neighbours by 2*WG_H cells; every WG_H steps each
@@ -1202,6 +1411,75 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
   if (itype == FQNM_I32)
     return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
   return by_pol<int64_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent temporal blocking (K_TBLOCK_PERSIST).
+// ---------------------------------------------------------------------------
+namespace {
+template <int POL, int V>
+const void* persist_fn() {
+  return reinterpret_cast<const void*>(&k_persist<POL, V>);
+}
+const void* persist_kernel(int pol, int vec) {
+#define FQNM_PERSIST_CASE(p)                                     \
+  case p:                                                        \
+    return vec == 4 ? persist_fn<p, 4>() : (vec == 8 ? persist_fn<p, 8>() : nullptr);
+  switch (pol) {
+    FQNM_PERSIST_CASE(P_LUT)
+    FQNM_PERSIST_CASE(P_EO)
+    FQNM_PERSIST_CASE(P_UPWIND_POS)
+    FQNM_PERSIST_CASE(P_UPWIND_NEG)
+    default: return nullptr;
+  }
+#undef FQNM_PERSIST_CASE
+}
+}  // namespace
+
+bool persist_geometry(int64_t n, int vec, int depth, int* khalo, int64_t* ntiles) {
+  if (vec != 4 && vec != 8) return false;
+  if (depth < 1 || n < 1) return false;
+  const int kh = scalar_halo(K_TBLOCK, vec, depth);
+  const int64_t tmax = 64 * vec - 2 * kh - vec;
+  if (tmax < kh) return false;
+  const int64_t nt = (n + tmax - 1) / tmax;
+  if (nt > INT32_MAX / 2) return false;
+  // the smallest tile: floor(n/nt) rounded down to vec, minus up to vec
+  if (n / nt - vec < kh) return false;
+  *khalo = kh;
+  *ntiles = nt;
+  return true;
+}
+
+bool persist_available(int itype, int pol, int vec, int bc) {
+  return itype == FQNM_I32 && bc == FQNM_BC_PERIODIC && persist_kernel(pol, vec) != nullptr;
+}
+
+hipError_t persist_fits(int pol, int vec, int64_t ntiles, bool* fits) {
+  const void* f = persist_kernel(pol, vec);
+  if (!f) return hipErrorInvalidValue;
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  *fits = (ntiles + 3) / 4 <= static_cast<int64_t>(per_cu) * cus;
+  return hipSuccess;
+}
+
+hipError_t launch_persist(int pol, int vec, const int32_t* src, int32_t* dst, int64_t n,
+                          int nsteps, int depth, const XParams& P, uint64_t* exch, uint32_t tag0,
+                          int* err, int spin, hipStream_t s) {
+  int khalo = 0;
+  int64_t ntiles = 0;
+  const void* f = persist_kernel(pol, vec);
+  if (!f || !persist_geometry(n, vec, depth, &khalo, &ntiles)) return hipErrorInvalidValue;
+  int nt32 = static_cast<int>(ntiles);
+  XParams Pc = P;
+  void* args[] = {const_cast<int32_t**>(&src), &dst, &n, &nsteps, &depth, &khalo, &nt32,
+                  &Pc, &exch, &tag0, &err, &spin};
+  const dim3 g(static_cast<unsigned>((ntiles + 3) / 4)), b(256);
+  return hipLaunchCooperativeKernel(f, g, b, args, 0, s);
 }
 
 int tblock_wg_positions(int nw, int vec) { return nw * 64 * vec - (nw - 1) * 2 * WG_H; }

@@ -115,27 +115,34 @@ def test_kind_parity_all_plans(flux, a, lut, bc, itype):
 
 
 @pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
-def test_table_tiles_at_the_slice_threshold(bc):
+@pytest.mark.parametrize("lo", [-192, -256])
+def test_table_tiles_at_the_slice_threshold(bc, lo):
     """Int32 tables: a wavefront copies its tile's slice of the table into LDS
     when the tile's states span fewer than 512 levels and otherwise evaluates
-    the split maps the table was built from.  Every 16th cell holds -256 and
-    every 16th (offset 8) holds 255 in the first half of the grid and 256 in
-    the second, so every tile spans exactly 511 or 512 levels; both sides of
-    the threshold must give the oracle's integers."""
+    the split maps the table was built from.  Every 16th cell holds lo and
+    every 16th (offset 8) holds -lo - 1 in the first half of the grid and -lo
+    in the second, so every tile spans exactly 2|lo| - 1 or 2|lo| levels:
+    with lo = -256 both sides of the threshold, with lo = -192 slices well
+    inside it.  Both must give the oracle's integers, for the single-launch
+    and the persistent plans."""
     rng = np.random.default_rng(77)
     n = 176 * 12
     half = n // 2
-    q0 = np.concatenate([rng.integers(-256, 256, half), rng.integers(-256, 257, n - half)])
-    q0[0::16] = -256
-    q0[8:half:16] = 255
-    q0[half + 8 - half % 16::16] = 256
+    hi = -lo
+    q0 = np.concatenate([rng.integers(lo, hi, half), rng.integers(lo, hi + 1, n - half)])
+    q0[0::16] = lo
+    q0[8:half:16] = hi - 1
+    q0[half + 8 - half % 16::16] = hi
     delta = 1e-3
-    prob = F.make_problem(F.FLUX_BURGERS_EO, delta, 0.45 / (256 * delta), n, bc=bc,
+    prob = F.make_problem(F.FLUX_BURGERS_EO, delta, 0.45 / (hi * delta), n, bc=bc,
                           itype=F.I32, eval_=F.EVAL_LUT)
     op = oracle_problem(prob)
     ref, led = O.step(op, q0, 100, return_ledger=True)
-    for plan in [None, (F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 8),
-                 (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 16, 32)]:
+    plans = [None, (F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 8),
+             (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 16, 32)]
+    if bc == F.BC_PERIODIC:
+        plans += [(10, 4, 40), (10, 4, 8), (10, 8, 24)]
+    for plan in plans:
         q, inv = gpu_run(prob, q0=q0.astype(np.int32), steps=100, plan=plan)
         assert np.array_equal(q, ref), plan
         assert inv["ledger"][0] == led
