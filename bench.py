@@ -244,6 +244,52 @@ def bench_batch(F, W, stream, G, reps=3):
                          "parity_vs_oracle": {"checked": checked, "bit_exact": ok}}}
 
 
+def bench_tiled_mix(F, W, stream, reps=3):
+    """Batches of instances outside the register-resident envelope (sizes up
+    to 2^20 cells, a third tabulated; int32, and int64), which run as tiled
+    work items, one launch per step block for all of them, against the
+    one-instance-at-a-time loop on the same GPU."""
+    import torch
+    res = {}
+    for width, count in ((32, 96), (64, 48)):
+        ws = W.w4_tiled_mix(count=count, seed=44 + width, width=width)
+        itype = F.I32 if width == 32 else F.I64
+        q0s = [F.fqnm_quantise(w.u0, w.delta, itype, stream) for w in ws]
+        probs = [F.make_problem(w.kind, w.delta, w.lam, w.n, itype=itype, a=w.a,
+                                eval_=F.EVAL_LUT if w.extra["lut"] else F.EVAL_DIRECT) for w in ws]
+        work = float(sum(w.n * w.steps for w in ws))
+        h = F.fqnm_batch_create(probs, q0s, [w.steps for w in ws], stream)
+        try:
+            ts = []
+            for r in range(reps + 1):
+                F.fqnm_batch_reset(h)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F.fqnm_batch_run(h)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            F.fqnm_batch_reset(h)
+            F.fqnm_batch_run_per_instance(h)  # creates the contexts, warm-up
+            F.fqnm_batch_reset(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F.fqnm_batch_run_per_instance(h)
+            torch.cuda.synchronize()
+            t_solo = time.perf_counter() - t0
+        finally:
+            F.fqnm_batch_destroy(h)
+        t_b = float(np.median(ts[1:]))
+        res[f"int{width}"] = {
+            "instances": count, "sizes": "log-uniform 2^12..2^20", "steps": "500..2000",
+            "tabulated": sum(1 for w in ws if w.extra["lut"]), "cell_updates": work,
+            "batched_ms": t_b * 1e3, "batched_cell_updates_per_s": work / t_b,
+            "per_instance_cell_updates_per_s": work / t_solo,
+            "speedup_vs_per_instance": t_solo / t_b}
+        log(f"[bench] tiled mix int{width}: batched {work / t_b:.3e}, "
+            f"per instance {work / t_solo:.3e} cell-updates/s")
+    return {"w4_tiled_mix": res}
+
+
 SERVE_COUNT = int(os.environ.get("FQNM_SERVE_COUNT", "1000"))
 SERVE_NMAX = int(os.environ.get("FQNM_SERVE_NMAX", str(1 << 18)))
 SERVE_SUBSET = int(os.environ.get("FQNM_SERVE_SUBSET", "150"))  # loads 0.5 and 0.9
@@ -630,6 +676,7 @@ def run_extras_only(args, F, W, plans, stream, G):
             extras[f"w3_r0.001_{tag}"] = {"cell_updates_per_s": w3.n * w3.steps / sec3}
     elif args.only == "batch":
         extras.update(bench_batch(F, W, stream, G))
+        extras.update(bench_tiled_mix(F, W, stream))
     elif args.only == "serve":
         extras.update(bench_serve(F, W, stream, G))
     elif args.only == "levels":
@@ -761,6 +808,7 @@ def main():
     # ---------------- batched: 4096 independent instances --------------------------
     if not args.no_extras and args.only in ("", "batch"):
         extras.update(bench_batch(F, W, stream, G))
+        extras.update(bench_tiled_mix(F, W, stream))
     # ---------------- served: Sod requests with Poisson arrivals -----------------------
     if not args.no_extras and args.only in ("", "serve"):
         extras.update(bench_serve(F, W, stream, G))

@@ -18,13 +18,19 @@
 // come from fixed slots, with no data-dependent register indexing.
 //
 // Instances outside that envelope (int64 cells, larger n, tabulated maps,
-// Lax-Friedrichs kinds) are advanced by the single-grid stepper on the same
-// stream.  The whole run is captured once into a HIP graph and replayed.
+// Lax-Friedrichs kinds) run as tiled work items: one launch per step block
+// advances every such instance that still has steps in that block, one
+// wavefront per (instance, tile), so they progress side by side rather than
+// one after another; the launch boundary is the barrier between an
+// instance's step blocks.  They run on a stream of their own, beside the
+// persistent kernels.  The whole run is captured once into a HIP graph and
+// replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "runtime.h"
@@ -346,8 +352,21 @@ struct fqnm_batch {
   ResidentLauncher launcher;
   int32_t n_resident = 0;
   int32_t n_class[RCLASSES] = {}; // resident instances per persistent kernel
-  std::vector<fqnm_ctx*> big;    // fallback single-grid contexts (borrowing their slices)
-  std::vector<int64_t> big_steps;
+  std::vector<fqnm_ctx*> big;    // single-grid contexts of the tiled instances (their slices,
+  std::vector<int64_t> big_steps; // second buffers, tables and constants)
+  // tiled work items: grids, per-launch entries, and the launches in order
+  TileGrid* d_grids = nullptr;
+  BlockGrid* d_entries = nullptr;
+  struct TLaunch {
+    int itype, pol, vec;
+    int64_t entry0;
+    int32_t nentries;
+    int64_t nitems;
+  };
+  std::vector<TLaunch> tlaunch;
+  std::vector<int32_t> copy_back;  // tiled instances whose last block wrote buf1
+  hipStream_t tstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -368,6 +387,11 @@ static void batch_free(fqnm_batch* b) {
   if (b->d_init) (void)hipFree(b->d_init);
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_grids) (void)hipFree(b->d_grids);
+  if (b->d_entries) (void)hipFree(b->d_entries);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->tstream) (void)hipStreamDestroy(b->tstream);
   resident_launcher_free(&b->launcher);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -384,15 +408,115 @@ static void batch_free(fqnm_batch* b) {
     }                                  \
   } while (0)
 
+// The tiled instances' step blocks: every instance takes its context's
+// temporally blocked plan (cells per lane 4 or 8; else 4 for int32 and 8 for
+// int64 with the default depth), and launch k of a (type, policy, cells per
+// lane) group covers the tiles of every instance of the group that has a
+// k-th step block.  Block k reads the instance's buffer k mod 2; an
+// instance with an odd number of blocks ends in its second buffer and is
+// copied back to its slice.
+static fqnm_status batch_plan_tiles(fqnm_batch* b) {
+  struct G { int itype, pol, vec, depth, khalo; int64_t ntiles, nblocks, steps; };
+  std::vector<G> gs;
+  std::vector<TileGrid> grids;
+  int64_t maxblocks = 0;
+  for (size_t i = 0; i < b->big.size(); ++i) {
+    fqnm_ctx* c = b->big[i];
+    const fqnm_plan dp = default_plan(c->prob);
+    int vec = c->plan.kernel == K_TBLOCK ? c->plan.vec : dp.vec;
+    int depth = c->plan.kernel == K_TBLOCK ? c->plan.depth : dp.depth;
+    if (vec != 4 && vec != 8) { vec = dp.vec; depth = dp.depth; }
+    int kh = scalar_halo(K_TBLOCK, vec, depth);
+    while (64 * vec - 2 * kh < 2 * vec && depth > 1) {  // keep some interior
+      depth /= 2;
+      kh = scalar_halo(K_TBLOCK, vec, depth);
+    }
+    if (!items_variant_available(c->prob.itype, c->pol, vec))
+      return fail(FQNM_ERR_UNSUPPORTED, "no tiled variant for a batch instance");
+    G g{c->prob.itype, c->pol, vec, depth, kh, 0, 0, b->big_steps[i]};
+    const int64_t T = 64 * vec - 2 * kh;
+    g.ntiles = (c->prob.n + T - 1) / T;
+    g.nblocks = (g.steps + depth - 1) / depth;
+    maxblocks = std::max(maxblocks, g.nblocks);
+    gs.push_back(g);
+    TileGrid tg;
+    std::memset(&tg, 0, sizeof tg);
+    tg.buf0 = c->buf[0];
+    tg.buf1 = c->buf[1];
+    tg.n = c->prob.n;
+    tg.bc = c->prob.bc;
+    tg.khalo = kh;
+    tg.ledger = c->d_ledger;
+    tg.P = c->xp;
+    grids.push_back(tg);
+    if (g.nblocks & 1) b->copy_back.push_back(static_cast<int32_t>(i));
+  }
+  // groups in a fixed order: (itype, pol, vec)
+  std::vector<std::tuple<int, int, int>> keys;
+  for (const G& g : gs) keys.emplace_back(g.itype, g.pol, g.vec);
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  std::vector<BlockGrid> entries;
+  for (int64_t k = 0; k < maxblocks; ++k) {
+    for (const auto& key : keys) {
+      fqnm_batch::TLaunch L{std::get<0>(key), std::get<1>(key), std::get<2>(key),
+                            static_cast<int64_t>(entries.size()), 0, 0};
+      for (size_t i = 0; i < gs.size(); ++i) {
+        const G& g = gs[i];
+        if (g.itype != L.itype || g.pol != L.pol || g.vec != L.vec || k >= g.nblocks) continue;
+        BlockGrid e;
+        std::memset(&e, 0, sizeof e);
+        e.first = L.nitems;
+        e.grid = static_cast<int32_t>(i);
+        e.ksteps = static_cast<int32_t>(std::min<int64_t>(g.depth, g.steps - k * g.depth));
+        e.parity = static_cast<int32_t>(k & 1);
+        entries.push_back(e);
+        L.nitems += g.ntiles;
+        ++L.nentries;
+      }
+      if (L.nentries > 0) b->tlaunch.push_back(L);
+    }
+  }
+  if (hipMalloc(&b->d_grids, sizeof(TileGrid) * grids.size()) != hipSuccess ||
+      (!entries.empty() && hipMalloc(&b->d_entries, sizeof(BlockGrid) * entries.size()) != hipSuccess))
+    return fail(FQNM_ERR_OOM, "batch tile table allocation failed");
+  B_HIP(hipMemcpyAsync(b->d_grids, grids.data(), sizeof(TileGrid) * grids.size(),
+                       hipMemcpyHostToDevice, b->stream), "copy tile grids");
+  if (!entries.empty())
+    B_HIP(hipMemcpyAsync(b->d_entries, entries.data(), sizeof(BlockGrid) * entries.size(),
+                         hipMemcpyHostToDevice, b->stream), "copy tile entries");
+  B_HIP(hipStreamSynchronize(b->stream), "sync");  // the host tables are freed on return
+  B_HIP(hipStreamCreateWithFlags(&b->tstream, hipStreamNonBlocking), "stream");
+  B_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "event");
+  B_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "event");
+  return FQNM_OK;
+}
+
 static fqnm_status batch_build_graph(fqnm_batch* b) {
   B_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t e = hipSuccess;
   fqnm_status st = FQNM_OK;
-  if (b->n_resident > 0)
+  const bool tiled = !b->tlaunch.empty() || !b->copy_back.empty();
+  if (tiled) {  // the tiled instances run on their own stream, forked and joined
+    e = hipEventRecord(b->ev_fork, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->tstream, b->ev_fork, 0);
+  }
+  if (e == hipSuccess && b->n_resident > 0)
     e = launch_resident(b->d_insts, b->d_order, b->n_resident, b->n_class, b->launcher,
                         static_cast<int32_t*>(b->d_state), b->stream);
-  for (size_t i = 0; i < b->big.size() && e == hipSuccess && st == FQNM_OK; ++i)
-    st = fqnm_step(b->big[i], b->big_steps[i]);
+  for (size_t i = 0; i < b->tlaunch.size() && e == hipSuccess; ++i) {
+    const auto& L = b->tlaunch[i];
+    e = launch_tile_items(L.itype, L.pol, L.vec, b->d_entries + L.entry0, L.nentries, L.nitems,
+                          b->d_grids, b->tstream);
+  }
+  for (size_t i = 0; i < b->copy_back.size() && e == hipSuccess; ++i) {
+    const fqnm_ctx* c = b->big[b->copy_back[i]];
+    e = launch_copy(c->buf[1], c->buf[0], c->state_bytes(), b->tstream);
+  }
+  if (tiled && e == hipSuccess) {
+    e = hipEventRecord(b->ev_join, b->tstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join, 0);
+  }
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); b->poisoned = true; return hip_fail(e, "batch launch"); }
@@ -507,6 +631,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       b->big_steps.push_back(steps[k]);
     }
   }
+  if (!st && !b->big.empty()) st = batch_plan_tiles(b);
   if (!st && hipStreamSynchronize(b->stream) != hipSuccess)
     st = fail(FQNM_ERR_DEVICE, "batch setup sync");
   if (!st) st = batch_build_graph(b);

@@ -52,6 +52,36 @@ bool tblock_wg_valid(int nw, int vec, int ksteps);
 hipError_t launch_tblock_wg(int nw, int vec, const int32_t* src, int32_t* dst, int64_t n,
                             int ksteps, const XParams& P, hipStream_t s);
 
+// Tiled work items of several grids, one step block per launch (K2 on each
+// item's tile).  A grid: its two buffers, size, boundary, halo, constants and
+// ledger.  A launch lists, per grid it covers, the steps of this block
+// (<= the grid's halo), which buffer it reads (buf0, or buf1 when `parity`
+// is set; it writes the other) and the index of the grid's first item
+// (entries in increasing `first`, the grid's tiles following it).
+struct TileGrid {
+  const void* buf0;
+  const void* buf1;
+  int64_t n;
+  int32_t bc;
+  int32_t khalo;
+  long long* ledger;
+  XParams P;
+};
+struct BlockGrid {
+  int64_t first;
+  int32_t grid;
+  int32_t ksteps;
+  int32_t parity;
+  int32_t pad_;
+};
+bool items_variant_available(int itype, int pol, int vec);
+// Device copy of `bytes` (a multiple of 4) by a kernel (no copy or memset
+// nodes in captured graphs).
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_tile_items(int itype, int pol, int vec, const BlockGrid* entries,
+                             int32_t nentries, int64_t nitems, const TileGrid* grids,
+                             hipStream_t s);
+
 // Persistent temporal blocking (K_TBLOCK_PERSIST): int32 states on periodic
 // grids, table or direct split policies, vec 4 or 8.  persist_geometry gives
 // the halo and the tile count of a plan (false if the grid cannot be tiled

@@ -329,15 +329,14 @@ __device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView&
   }
 }
 
+// One wavefront's pass over tile `tile` of a grid (the body of K2, shared
+// with the batch's tiled work items): load the window, advance it ksteps
+// steps, store the tile interior, add the boundary counts to the ledger.
 template <typename IT, int POL, int V>
-__global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* __restrict__ dst,
-                                                int64_t n, int bc, int ksteps, int khalo,
-                                                int64_t ntiles, XParams P,
-                                                long long* __restrict__ ledger) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
-  if (tile >= ntiles) return;  // the whole wavefront leaves together
+__device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __restrict__ dst,
+                                            int64_t n, int bc, int ksteps, int khalo, int64_t tile,
+                                            const XParams& P, long long* __restrict__ ledger,
+                                            int wave, int lane) {
   const int64_t T = 64 * V - 2 * khalo;
   const int64_t tstart = tile * T;
   const int64_t wstart = tstart - khalo;
@@ -441,6 +440,49 @@ __global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* 
   }
   if (led != 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(ledger), static_cast<unsigned long long>(led));
+}
+
+template <typename IT, int POL, int V>
+__global__ __launch_bounds__(256) void k_tblock(const IT* __restrict__ src, IT* __restrict__ dst,
+                                                int64_t n, int bc, int ksteps, int khalo,
+                                                int64_t ntiles, XParams P,
+                                                long long* __restrict__ ledger) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= ntiles) return;  // the whole wavefront leaves together
+  tblock_tile<IT, POL, V>(src, dst, n, bc, ksteps, khalo, tile, P, ledger, wave, lane);
+}
+
+// Tiled work items of many grids (the batch's instances outside the
+// register-resident envelope): one launch runs one step block of every grid
+// listed for it, one wavefront per (grid, tile) item, each item K2 on that
+// tile for the grid's steps of this block.  The grids of a launch share the
+// storage type, policy and cells per lane; each has its own buffers,
+// constants and halo.  entries[e] covers the launch's items
+// [entries[e].first, entries[e+1].first); a wavefront finds its entry by
+// binary search (the same for every lane).  The launch boundary is the
+// barrier between a grid's step blocks.
+template <typename IT, int POL, int V>
+__global__ __launch_bounds__(256) void k_tblock_items(const BlockGrid* __restrict__ entries,
+                                                      int32_t nentries, int64_t nitems,
+                                                      const TileGrid* __restrict__ grids) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  if (w >= nitems) return;  // the whole wavefront leaves together
+  int32_t lo = 0, hi = nentries - 1;  // last entry with first <= w
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (entries[mid].first <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const BlockGrid e = entries[lo];
+  const TileGrid& g = grids[e.grid];
+  const IT* src = static_cast<const IT*>(e.parity ? g.buf1 : g.buf0);
+  IT* dst = static_cast<IT*>(const_cast<void*>(e.parity ? g.buf0 : g.buf1));
+  tblock_tile<IT, POL, V>(src, dst, g.n, g.bc, e.ksteps, g.khalo, w - e.first, g.P, g.ledger,
+                          wave, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1411,6 +1453,67 @@ hipError_t launch_scalar(int itype, int pol, int kernel, int vec, const void* sr
   if (itype == FQNM_I32)
     return by_pol<int32_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
   return by_pol<int64_t>(pol, kernel, vec, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled work items of several grids (the batch).
+// ---------------------------------------------------------------------------
+namespace {
+template <typename IT, int POL>
+hipError_t items_by_vec(int vec, const BlockGrid* entries, int32_t nentries, int64_t nitems,
+                        const TileGrid* grids, hipStream_t s) {
+  const dim3 g(static_cast<unsigned>((nitems + 3) / 4)), b(256);
+  if (vec == 4) k_tblock_items<IT, POL, 4><<<g, b, 0, s>>>(entries, nentries, nitems, grids);
+  else if (vec == 8) k_tblock_items<IT, POL, 8><<<g, b, 0, s>>>(entries, nentries, nitems, grids);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+}  // namespace
+
+namespace {
+__global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                             int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+}  // namespace
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  if (bytes % 4 != 0) return hipErrorInvalidValue;
+  const int64_t n = static_cast<int64_t>(bytes / 4);
+  if (n == 0) return hipSuccess;
+  k_copy_words<<<grid_for(n, 256), 256, 0, s>>>(static_cast<const uint32_t*>(src),
+                                                static_cast<uint32_t*>(dst), n);
+  return hipGetLastError();
+}
+
+bool items_variant_available(int itype, int pol, int vec) {
+  return (vec == 4 || vec == 8) && pol >= 0 && pol < P_COUNT && (itype == FQNM_I32 || itype == FQNM_I64);
+}
+
+hipError_t launch_tile_items(int itype, int pol, int vec, const BlockGrid* entries,
+                             int32_t nentries, int64_t nitems, const TileGrid* grids,
+                             hipStream_t s) {
+  if (nitems <= 0 || nentries <= 0) return hipSuccess;
+  if (!items_variant_available(itype, pol, vec) || (nitems + 3) / 4 > INT32_MAX)
+    return hipErrorInvalidValue;
+#define FQNM_ITEMS_CASE(p)                                                                   \
+  case p:                                                                                    \
+    return itype == FQNM_I32 ? items_by_vec<int32_t, p>(vec, entries, nentries, nitems, grids, s) \
+                             : items_by_vec<int64_t, p>(vec, entries, nentries, nitems, grids, s);
+  switch (pol) {
+    FQNM_ITEMS_CASE(P_UPWIND_POS)
+    FQNM_ITEMS_CASE(P_UPWIND_NEG)
+    FQNM_ITEMS_CASE(P_EO)
+    FQNM_ITEMS_CASE(P_GODUNOV)
+    FQNM_ITEMS_CASE(P_MURMAN_ROE)
+    FQNM_ITEMS_CASE(P_LF_LINEAR)
+    FQNM_ITEMS_CASE(P_LF_BURGERS)
+    FQNM_ITEMS_CASE(P_LUT)
+    default: return hipErrorInvalidValue;
+  }
+#undef FQNM_ITEMS_CASE
 }
 
 // ---------------------------------------------------------------------------

@@ -176,6 +176,35 @@ def w4_batch(count=4096, seed=4, nmin=256, nmax=65536, smin=500, smax=5000, delt
     return out
 
 
+def w4_tiled_mix(count=192, seed=44, width=32, nmin=1 << 12, nmax=1 << 20, smin=500,
+                 smax=2000, delta=1e-5):
+    """Instances outside the batch's register-resident envelope (and a few
+    inside it): the W4 families with sizes log-uniform in [nmin, nmax] (most
+    above 65536 cells), every third one tabulated (eval LUT).  Drawn per
+    instance in this order: kind, N, steps, b, A, m, theta, h, xs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        adv = rng.uniform() < 0.5
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        steps = int(rng.integers(smin, smax + 1))
+        b = rng.uniform(-0.25, 0.75)
+        A = rng.uniform(0.2, 1.0)
+        m = int(rng.integers(1, 4))
+        theta = rng.uniform(0.0, 2 * np.pi)
+        h = rng.uniform(0.2, 1.0)
+        xs = rng.uniform(0.0, 1.0)
+        u0 = sine_step_field(grid(n), b, A, m, theta, h, xs)
+        if adv:
+            s = Scalar(UPWIND, delta, 0.5, u0, steps, PERIODIC, width, a=1.0, name=f"mix{k}-adv")
+        else:
+            s = Scalar(BURGERS_EO, delta, burgers_cfl_lambda(u0, 0.45), u0, steps, PERIODIC, width,
+                       name=f"mix{k}-burgers")
+        s.extra = {"lut": k % 3 == 0}
+        out.append(s)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Euler / Sod
 # ---------------------------------------------------------------------------

@@ -173,3 +173,40 @@ def test_batch_rejects_invalid_instances():
     with pytest.raises(F.FqnmError) as e:
         F.fqnm_batch_create([p, bad], [q0.astype(np.int32)] * 2, [s, s])
     assert e.value.status == F.ERR_CFL
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_tiled_instances_run_together_and_match_oracle(width):
+    """Instances outside the register-resident envelope (tabulated maps,
+    64-bit states, more than 65536 cells) run as tiled work items, one launch
+    per step block for all of them: every one equals the oracle and the
+    per-instance loop."""
+    ws = W.w4_tiled_mix(count=24, seed=9, width=width, nmin=1 << 10, nmax=1 << 17, smin=50,
+                        smax=300)
+    itype = F.I32 if width == 32 else F.I64
+    dt = np.int32 if width == 32 else np.int64
+    probs, q0s, ops = [], [], []
+    for w in ws:
+        probs.append(F.make_problem(w.kind, w.delta, w.lam, w.n, itype=itype, a=w.a,
+                                    eval_=F.EVAL_LUT if w.extra["lut"] else F.EVAL_DIRECT))
+        q0s.append(O.quantise(w.u0, w.delta, width))
+        ops.append(O.Problem(O.UPWIND if w.kind == W.UPWIND else O.BURGERS_EO, w.delta, w.lam,
+                             width=width, a=w.a))
+    steps = [w.steps for w in ws]
+    h = F.fqnm_batch_create(probs, [q.astype(dt) for q in q0s], steps)
+    try:
+        F.fqnm_batch_run(h)
+        got = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+        F.fqnm_batch_reset(h)
+        F.fqnm_batch_run(h)
+        again = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+        F.fqnm_batch_reset(h)
+        F.fqnm_batch_run_per_instance(h)
+        solo = [F.fqnm_batch_get_state(h, i, p).astype(np.int64) for i, p in enumerate(probs)]
+    finally:
+        F.fqnm_batch_destroy(h)
+    for i in range(len(ws)):
+        ref = O.step(ops[i], q0s[i], steps[i], omp=True)
+        assert np.array_equal(got[i], ref), (i, ws[i].n, ws[i].extra)
+        assert np.array_equal(again[i], ref), i
+        assert np.array_equal(solo[i], ref), i
