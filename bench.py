@@ -206,18 +206,27 @@ def bench_batch(F, W, stream, G, reps=3):
     work = float(sum(n * s for n, s in zip(sizes, steps)))
     h = F.fqnm_batch_create(probs, q0s, steps, stream)
     try:
-        F.fqnm_batch_reset(h)
-        F.fqnm_batch_run(h)  # warm-up
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
+        def timed():
             F.fqnm_batch_reset(h)
+            F.fqnm_batch_run(h)  # warm-up
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            F.fqnm_batch_run(h)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        log(f"[bench] W4 batched {min(ts)*1e3:.1f} ms; per-instance loop follows")
+            out = []
+            for _ in range(reps):
+                F.fqnm_batch_reset(h)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F.fqnm_batch_run(h)
+                torch.cuda.synchronize()
+                out.append(time.perf_counter() - t0)
+            return out
+        F.fqnm_batch_set_config(h)  # the default layout
+        t_default = float(np.median(timed()))
+        t0 = time.perf_counter()
+        cfg = F.fqnm_batch_autotune(h)
+        t_tune = time.perf_counter() - t0
+        ts = timed()
+        log(f"[bench] W4 batched {min(ts)*1e3:.1f} ms (default layout {t_default*1e3:.1f} ms, "
+            f"autotuned {cfg}); per-instance loop follows")
         checked = ok = 0
         for k, p in enumerate(probs):
             r = parity(f"w4_{k}", F.fqnm_batch_get_state(h, k, p), G)
@@ -241,6 +250,8 @@ def bench_batch(F, W, stream, G, reps=3):
                          "per_instance_ms": t_solo * 1e3,
                          "per_instance_cell_updates_per_s": work / t_solo,
                          "speedup_vs_per_instance": t_solo / t_b,
+                         "layout": {"autotuned": cfg, "autotune_s": t_tune,
+                                    "default_layout_ms": t_default * 1e3},
                          "parity_vs_oracle": {"checked": checked, "bit_exact": ok}}}
 
 
@@ -260,6 +271,7 @@ def bench_tiled_mix(F, W, stream, reps=3):
         work = float(sum(w.n * w.steps for w in ws))
         h = F.fqnm_batch_create(probs, q0s, [w.steps for w in ws], stream)
         try:
+            cfg = F.fqnm_batch_autotune(h)
             ts = []
             for r in range(reps + 1):
                 F.fqnm_batch_reset(h)
@@ -284,7 +296,7 @@ def bench_tiled_mix(F, W, stream, reps=3):
             "tabulated": sum(1 for w in ws if w.extra["lut"]), "cell_updates": work,
             "batched_ms": t_b * 1e3, "batched_cell_updates_per_s": work / t_b,
             "per_instance_cell_updates_per_s": work / t_solo,
-            "speedup_vs_per_instance": t_solo / t_b}
+            "speedup_vs_per_instance": t_solo / t_b, "layout": cfg}
         log(f"[bench] tiled mix int{width}: batched {work / t_b:.3e}, "
             f"per instance {work / t_solo:.3e} cell-updates/s")
     return {"w4_tiled_mix": res}

@@ -348,6 +348,39 @@ typedef struct fqnm_batch fqnm_batch;
 fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
                               const int64_t* steps, int32_t count, void* hip_stream,
                               fqnm_batch** out);
+/* How a batch lays out its work.  Register-resident instances: those of at
+ * most class0_max_cells cells (<= 16384) run on 512-thread workgroups using
+ * at most class0_lanes lanes (128, 256 or 512: cells per lane is the
+ * smallest power of two that fits, at most 32); with wide_split_class 1 (or
+ * 0), split kinds of up to 32768 cells run on 512 threads with 64 cells per
+ * lane, with 2 they join the larger instances on 1024-thread workgroups.
+ * Tiled instances: tiled_vec cells per lane (4 or 8) and tiled_depth steps
+ * per block, or each instance's own single-grid plan where 0.  Every field
+ * zero means the library's default layout. */
+typedef struct {
+  int32_t class0_max_cells;
+  int32_t class0_lanes;
+  int32_t wide_split_class;
+  int32_t tiled_vec;
+  int32_t tiled_depth;
+  int32_t reserved;     /* must be 0 */
+} fqnm_batch_config;
+
+/* The batch's current layout (the default until set or tuned). */
+fqnm_status fqnm_batch_get_config(fqnm_batch* b, fqnm_batch_config* out);
+/* Lay the batch out anew (rebuilds its instance tables and graph; the
+ * instances' states are not changed).  FQNM_ERR_ARG for values outside the
+ * ranges above.  Syncs. */
+fqnm_status fqnm_batch_set_config(fqnm_batch* b, const fqnm_batch_config* cfg);
+/* Time candidate layouts of this batch -- the class boundary, lanes per
+ * resident instance, the wide split class, and the tiled instances' cells
+ * per lane and depth -- each on the real instances (the better of two runs,
+ * HIP events on the library's stream), keep the fastest, and remember it for
+ * batches of the same shape (count, storage type and a histogram of the
+ * instances' sizes) in this process.  Every instance is reset to its initial
+ * state afterwards.  Syncs. */
+fqnm_status fqnm_batch_autotune(fqnm_batch* b);
+
 /* Restore every instance to its initial state (for repeated runs). Async. */
 fqnm_status fqnm_batch_reset(fqnm_batch* b);
 /* Advance every instance by its own step count in one batched run. Async. */

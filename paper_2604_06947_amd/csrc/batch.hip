@@ -28,8 +28,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -225,16 +229,42 @@ bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps) {
 }
 
 void resident_layout(int64_t n, int pol, int32_t* vec, int32_t* cls) {
-  if (n <= int64_t(BT) * 32) {
+  fqnm_batch_config cfg;
+  std::memset(&cfg, 0, sizeof cfg);
+  resident_layout_cfg(n, pol, cfg, vec, cls);
+}
+
+void resident_layout_cfg(int64_t n, int pol, const fqnm_batch_config& cfg, int32_t* vec,
+                         int32_t* cls) {
+  const int64_t c0max = cfg.class0_max_cells ? cfg.class0_max_cells : int64_t(BT) * 32;
+  const int lanes = cfg.class0_lanes ? cfg.class0_lanes : BT;
+  const bool wide = cfg.wide_split_class != 2;
+  if (n <= c0max) {
     *cls = 0;
-    *vec = pick_vec(n, BT);
-  } else if (!two_point(pol) && n <= int64_t(BT) * 64) {
+    *vec = pick_vec(n, lanes);
+    if (*vec > 32) *vec = pick_vec(n, BT);  // class 0 keeps at most 32 cells per lane
+  } else if (wide && !two_point(pol) && n <= int64_t(BT) * 64) {
     *cls = 1;
     *vec = 64;
   } else {
     *cls = 2;
     *vec = pick_vec(n, BT2);
   }
+}
+
+bool batch_config_valid(const fqnm_batch_config& c) {
+  if (c.reserved != 0) return false;
+  if (c.class0_max_cells < 0 || c.class0_max_cells > BT * 32) return false;
+  if (c.class0_lanes != 0 && c.class0_lanes != 128 && c.class0_lanes != 256 &&
+      c.class0_lanes != BT)
+    return false;
+  if (c.wide_split_class < 0 || c.wide_split_class > 2) return false;
+  if (c.tiled_vec != 0 && c.tiled_vec != 4 && c.tiled_vec != 8) return false;
+  if (c.tiled_depth < 0 || (c.tiled_depth > 0 && c.tiled_vec == 0)) return false;
+  if (c.tiled_vec && c.tiled_depth &&
+      64 * c.tiled_vec - 2 * scalar_halo(K_TBLOCK, c.tiled_vec, c.tiled_depth) < 2 * c.tiled_vec)
+    return false;
+  return true;
 }
 
 int resident_grid_of(int cls) {
@@ -365,6 +395,8 @@ struct fqnm_batch {
   };
   std::vector<TLaunch> tlaunch;
   std::vector<int32_t> copy_back;  // tiled instances whose last block wrote buf1
+  std::vector<BInst> res_base;     // resident instances, before the layout fills vec, cls
+  fqnm_batch_config cfg{};         // current layout
   hipStream_t tstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
@@ -415,8 +447,14 @@ static void batch_free(fqnm_batch* b) {
 // k-th step block.  Block k reads the instance's buffer k mod 2; an
 // instance with an odd number of blocks ends in its second buffer and is
 // copied back to its slice.
-static fqnm_status batch_plan_tiles(fqnm_batch* b) {
+static fqnm_status batch_plan_tiles(fqnm_batch* b, const fqnm_batch_config& cfg) {
   struct G { int itype, pol, vec, depth, khalo; int64_t ntiles, nblocks, steps; };
+  b->tlaunch.clear();
+  b->copy_back.clear();
+  if (b->d_grids) (void)hipFree(b->d_grids);
+  if (b->d_entries) (void)hipFree(b->d_entries);
+  b->d_grids = nullptr;
+  b->d_entries = nullptr;
   std::vector<G> gs;
   std::vector<TileGrid> grids;
   int64_t maxblocks = 0;
@@ -426,6 +464,8 @@ static fqnm_status batch_plan_tiles(fqnm_batch* b) {
     int vec = c->plan.kernel == K_TBLOCK ? c->plan.vec : dp.vec;
     int depth = c->plan.kernel == K_TBLOCK ? c->plan.depth : dp.depth;
     if (vec != 4 && vec != 8) { vec = dp.vec; depth = dp.depth; }
+    if (cfg.tiled_vec) vec = cfg.tiled_vec;
+    if (cfg.tiled_depth) depth = cfg.tiled_depth;
     int kh = scalar_halo(K_TBLOCK, vec, depth);
     while (64 * vec - 2 * kh < 2 * vec && depth > 1) {  // keep some interior
       depth /= 2;
@@ -486,10 +526,84 @@ static fqnm_status batch_plan_tiles(fqnm_batch* b) {
     B_HIP(hipMemcpyAsync(b->d_entries, entries.data(), sizeof(BlockGrid) * entries.size(),
                          hipMemcpyHostToDevice, b->stream), "copy tile entries");
   B_HIP(hipStreamSynchronize(b->stream), "sync");  // the host tables are freed on return
-  B_HIP(hipStreamCreateWithFlags(&b->tstream, hipStreamNonBlocking), "stream");
-  B_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "event");
-  B_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "event");
+  if (!b->tstream) {
+    B_HIP(hipStreamCreateWithFlags(&b->tstream, hipStreamNonBlocking), "stream");
+    B_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "event");
+    B_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "event");
+  }
   return FQNM_OK;
+}
+
+// The resident instances' table under a layout: cells per lane and class of
+// every instance, longest work first.
+static fqnm_status batch_plan_resident(fqnm_batch* b, const fqnm_batch_config& cfg) {
+  if (b->n_resident == 0) return FQNM_OK;
+  std::vector<BInst> insts = b->res_base;
+  for (BInst& I : insts) resident_layout_cfg(I.n, I.pol, cfg, &I.vec, &I.cls);
+  std::vector<int32_t> order(b->n_resident);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return int64_t(insts[x].n) * insts[x].steps > int64_t(insts[y].n) * insts[y].steps;
+  });
+  if (!b->d_insts && (hipMalloc(&b->d_insts, sizeof(BInst) * insts.size()) != hipSuccess ||
+                      hipMalloc(&b->d_order, sizeof(int32_t) * order.size()) != hipSuccess))
+    return fail(FQNM_ERR_OOM, "batch table allocation failed");
+  B_HIP(hipMemcpyAsync(b->d_insts, insts.data(), sizeof(BInst) * insts.size(),
+                       hipMemcpyHostToDevice, b->stream), "copy batch table");
+  B_HIP(hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
+                       hipMemcpyHostToDevice, b->stream), "copy batch order");
+  B_HIP(hipStreamSynchronize(b->stream), "sync");
+  resident_class_counts(insts.data(), b->n_resident, b->n_class);
+  return FQNM_OK;
+}
+
+static fqnm_status batch_build_graph(fqnm_batch* b);
+
+// Lay the batch out under cfg: tables, tiled launches and the graph.
+static fqnm_status batch_configure(fqnm_batch* b, const fqnm_batch_config& cfg) {
+  if (!batch_config_valid(cfg)) return fail(FQNM_ERR_ARG, "invalid batch configuration");
+  if (b->stream) B_HIP(hipStreamSynchronize(b->stream), "sync");
+  fqnm_status st = batch_plan_resident(b, cfg);
+  if (!st && !b->big.empty()) st = batch_plan_tiles(b, cfg);
+  if (st) return st;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  st = batch_build_graph(b);
+  if (!st) b->cfg = cfg;
+  return st;
+}
+
+// In-process layout cache keyed by the shape of a batch: instance count,
+// storage type, resident count and a histogram of log2 sizes (with the
+// step counts' total, in powers of two).
+static std::mutex g_bcfg_mu;
+static std::map<std::string, fqnm_batch_config> g_bcfg;
+
+static std::string batch_shape_key(const fqnm_batch* b) {
+  std::vector<int> hist(40, 0);
+  double work = 0.0;
+  for (int32_t k = 0; k < b->count; ++k) {
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= b->probs[k].n && lg < 39) ++lg;
+    ++hist[lg];
+    work += static_cast<double>(b->probs[k].n) * static_cast<double>(b->steps[k]);
+  }
+  std::string key = "c" + std::to_string(b->count) + "_i" + std::to_string(b->probs[0].itype) +
+                    "_r" + std::to_string(b->n_resident) + "_w" +
+                    std::to_string(static_cast<int>(std::log2(work + 1.0)));
+  for (int i = 0; i < 40; ++i)
+    if (hist[i]) key += "_" + std::to_string(i) + ":" + std::to_string(hist[i]);
+  return key;
+}
+
+static bool lookup_batch_config(const std::string& key, fqnm_batch_config* out) {
+  std::lock_guard<std::mutex> g(g_bcfg_mu);
+  auto it = g_bcfg.find(key);
+  if (it == g_bcfg.end()) return false;
+  *out = it->second;
+  return true;
 }
 
 static fqnm_status batch_build_graph(fqnm_batch* b) {
@@ -540,8 +654,6 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
   b->count = count;
   b->probs.assign(probs, probs + count);
   b->steps.assign(steps, steps + count);
-  std::vector<BInst> host_insts;
-  std::vector<int32_t> res_ids;
   // validate and lay out: every instance starts on a 16-byte boundary
   for (int32_t k = 0; k < count; ++k) {
     const fqnm_problem& p = probs[k];
@@ -574,13 +686,11 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       I.n = static_cast<int32_t>(p.n);
       I.steps = static_cast<int32_t>(steps[k]);
       I.pol = pol;
-      resident_layout(p.n, pol, &I.vec, &I.cls);
       I.bc = p.bc;
       XParams x = xparams_of(p);
       I.c = x.c;
       I.h = x.h;
-      res_ids.push_back(static_cast<int32_t>(host_insts.size()));
-      host_insts.push_back(I);
+      b->res_base.push_back(I);
     }
   }
   const size_t es = esize_of(probs[0]);
@@ -601,25 +711,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
   if (!st && hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice,
                             b->stream) != hipSuccess)
     st = fail(FQNM_ERR_DEVICE, "copy state");
-  b->n_resident = static_cast<int32_t>(host_insts.size());
-  if (!st && b->n_resident > 0) {
-    // longest work first
-    std::vector<int32_t> order(b->n_resident);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-      return int64_t(host_insts[x].n) * host_insts[x].steps >
-             int64_t(host_insts[y].n) * host_insts[y].steps;
-    });
-    if (hipMalloc(&b->d_insts, sizeof(BInst) * host_insts.size()) != hipSuccess ||
-        hipMalloc(&b->d_order, sizeof(int32_t) * order.size()) != hipSuccess)
-      st = fail(FQNM_ERR_OOM, "batch table allocation failed");
-    if (!st && (hipMemcpyAsync(b->d_insts, host_insts.data(), sizeof(BInst) * host_insts.size(),
-                               hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-                hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * order.size(),
-                               hipMemcpyHostToDevice, b->stream) != hipSuccess))
-      st = fail(FQNM_ERR_DEVICE, "copy batch table");
-    resident_class_counts(host_insts.data(), b->n_resident, b->n_class);
-  }
+  b->n_resident = static_cast<int32_t>(b->res_base.size());
   // instances outside the resident envelope: single-grid contexts on their slices
   for (int32_t k = 0; k < count && !st; ++k) {
     if (b->resident[k]) continue;
@@ -631,10 +723,13 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
       b->big_steps.push_back(steps[k]);
     }
   }
-  if (!st && !b->big.empty()) st = batch_plan_tiles(b);
   if (!st && hipStreamSynchronize(b->stream) != hipSuccess)
     st = fail(FQNM_ERR_DEVICE, "batch setup sync");
-  if (!st) st = batch_build_graph(b);
+  if (!st) {
+    fqnm_batch_config cfg;
+    if (!lookup_batch_config(batch_shape_key(b), &cfg)) std::memset(&cfg, 0, sizeof cfg);
+    st = batch_configure(b, cfg);
+  }
   if (st) { batch_free(b); return st; }
   *out = b;
   return FQNM_OK;
@@ -695,6 +790,88 @@ fqnm_status fqnm_batch_get_state(fqnm_batch* b, int32_t idx, void* q_host) {
 
 fqnm_status fqnm_batch_destroy(fqnm_batch* b) {
   batch_free(b);
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_batch_get_config(fqnm_batch* b, fqnm_batch_config* out) {
+  if (!b || !out) return fail(FQNM_ERR_ARG, "NULL argument");
+  *out = b->cfg;
+  return FQNM_OK;
+}
+
+fqnm_status fqnm_batch_set_config(fqnm_batch* b, const fqnm_batch_config* cfg) {
+  if (!b || !cfg) return fail(FQNM_ERR_ARG, "NULL argument");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  return batch_configure(b, *cfg);
+}
+
+fqnm_status fqnm_batch_autotune(fqnm_batch* b) {
+  if (!b) return fail(FQNM_ERR_ARG, "batch is NULL");
+  if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
+  const size_t es = esize_of(b->probs[0]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  B_HIP(hipEventCreate(&e0), "event");
+  B_HIP(hipEventCreate(&e1), "event");
+  // one configured run: reset from the initial states, replay, the better of two
+  auto trial = [&](const fqnm_batch_config& c, float* ms) -> fqnm_status {
+    fqnm_status st = batch_configure(b, c);
+    if (st) return st;
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      B_HIP(hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice,
+                           b->stream), "reset");
+      B_HIP(hipEventRecord(e0, b->stream), "record");
+      B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
+      B_HIP(hipEventRecord(e1, b->stream), "record");
+      B_HIP(hipEventSynchronize(e1), "sync");
+      float t = 0.f;
+      B_HIP(hipEventElapsedTime(&t, e0, e1), "elapsed");
+      best = t < best ? t : best;
+    }
+    *ms = best;
+    return FQNM_OK;
+  };
+  fqnm_batch_config best;
+  std::memset(&best, 0, sizeof best);
+  float best_ms = 1e30f;
+  fqnm_status st = FQNM_OK;
+  if (b->n_resident > 0) {
+    for (int c0 : {BT * 32, BT * 16})
+      for (int lanes : {BT, 256, 128})
+        for (int wide : {1, 2}) {
+          fqnm_batch_config c = best;
+          c.class0_max_cells = c0;
+          c.class0_lanes = lanes;
+          c.wide_split_class = wide;
+          float ms = 0.f;
+          if ((st = trial(c, &ms))) break;
+          if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+  }
+  if (!st && !b->big.empty()) {
+    const fqnm_batch_config base = best;
+    best_ms = 1e30f;
+    const int cand[][2] = {{0, 0}, {4, 24}, {4, 40}, {8, 24}, {8, 48}};
+    for (const auto& vd : cand) {
+      fqnm_batch_config c = base;
+      c.tiled_vec = vd[0];
+      c.tiled_depth = vd[1];
+      if (!batch_config_valid(c)) continue;
+      float ms = 0.f;
+      if ((st = trial(c, &ms))) break;
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!st) st = batch_configure(b, best);
+  if (!st && hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice,
+                            b->stream) != hipSuccess)
+    st = fail(FQNM_ERR_DEVICE, "reset");
+  if (!st && hipStreamSynchronize(b->stream) != hipSuccess) st = fail(FQNM_ERR_DEVICE, "sync");
+  if (st) { b->poisoned = true; return st; }
+  std::lock_guard<std::mutex> g(g_bcfg_mu);
+  g_bcfg[batch_shape_key(b)] = best;
   return FQNM_OK;
 }
 

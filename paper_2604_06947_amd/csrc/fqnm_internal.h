@@ -204,6 +204,10 @@ struct ResidentInst {
 bool resident_eligible(const fqnm_problem& p, int pol, int64_t steps);
 // cells per lane and kernel class of a resident instance of n cells
 void resident_layout(int64_t n, int pol, int32_t* vec, int32_t* cls);
+// The same under a batch layout (fqnm_batch_config; zero fields: default).
+void resident_layout_cfg(int64_t n, int pol, const fqnm_batch_config& cfg, int32_t* vec,
+                         int32_t* cls);
+bool batch_config_valid(const fqnm_batch_config& c);
 // Launch state of the persistent batch kernels (one per register-footprint
 // class): the classes other than the widest nonempty one run on the side
 // streams, forked from the caller's stream by `fork` and joined back by

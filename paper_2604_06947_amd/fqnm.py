@@ -50,7 +50,8 @@ EXPORTED = [
     "fqnm_invariants_get_noalloc", "fqnm_get_plan",
     "fqnm_set_plan", "fqnm_autotune", "fqnm_destroy", "fqnm_batch_create", "fqnm_batch_reset",
     "fqnm_batch_run", "fqnm_batch_run_per_instance", "fqnm_batch_get_state",
-    "fqnm_batch_destroy", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
+    "fqnm_batch_destroy", "fqnm_batch_get_config", "fqnm_batch_set_config",
+    "fqnm_batch_autotune", "fqnm_fp64_selfcheck", "fqnm_quantise", "fqnm_server_create", "fqnm_server_submit", "fqnm_server_poll",
     "fqnm_server_drain", "fqnm_server_stats_get", "fqnm_server_now", "fqnm_server_destroy",
     "fqnm_level_histogram", "fqnm_entropy", "fqnm_step_transitions", "fqnm_create_nd",
 ]
@@ -80,6 +81,12 @@ class fqnm_invariants(C.Structure):
 class fqnm_plan(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("vec", C.c_int32), ("depth", C.c_int32),
                 ("eval", C.c_int32)]
+
+
+class fqnm_batch_config(C.Structure):
+    _fields_ = [("class0_max_cells", C.c_int32), ("class0_lanes", C.c_int32),
+                ("wide_split_class", C.c_int32), ("tiled_vec", C.c_int32),
+                ("tiled_depth", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fqnm_completion(C.Structure):
@@ -134,6 +141,9 @@ def lib():
             "fqnm_batch_run_per_instance": ([vp], C.c_int),
             "fqnm_batch_get_state": ([vp, i32, vp], C.c_int),
             "fqnm_batch_destroy": ([vp], C.c_int),
+            "fqnm_batch_get_config": ([vp, C.POINTER(fqnm_batch_config)], C.c_int),
+            "fqnm_batch_set_config": ([vp, C.POINTER(fqnm_batch_config)], C.c_int),
+            "fqnm_batch_autotune": ([vp], C.c_int),
             "fqnm_server_create": ([C.c_size_t, i32, vp, C.POINTER(vp)], C.c_int),
             "fqnm_server_submit": ([vp, P, vp, i64, vp, C.POINTER(C.c_uint64)], C.c_int),
             "fqnm_server_poll": ([vp, C.POINTER(fqnm_completion), i32, C.POINTER(i32)], C.c_int),
@@ -407,6 +417,26 @@ def fqnm_batch_destroy(h):
 # --------------------------------------------------------------------------
 # serving
 # --------------------------------------------------------------------------
+_BATCH_CFG_FIELDS = ("class0_max_cells", "class0_lanes", "wide_split_class", "tiled_vec",
+                     "tiled_depth")
+
+
+def fqnm_batch_get_config(h):
+    c = fqnm_batch_config()
+    _check(lib().fqnm_batch_get_config(h, C.byref(c)))
+    return {k: getattr(c, k) for k in _BATCH_CFG_FIELDS}
+
+
+def fqnm_batch_set_config(h, **kw):
+    c = fqnm_batch_config(*[int(kw.get(k, 0)) for k in _BATCH_CFG_FIELDS], 0)
+    _check(lib().fqnm_batch_set_config(h, C.byref(c)))
+
+
+def fqnm_batch_autotune(h):
+    _check(lib().fqnm_batch_autotune(h))
+    return fqnm_batch_get_config(h)
+
+
 def fqnm_server_create(budget_bytes, tick_steps, stream=None):
     h = C.c_void_p()
     _check(lib().fqnm_server_create(int(budget_bytes), int(tick_steps), stream, C.byref(h)))

@@ -210,3 +210,49 @@ def test_tiled_instances_run_together_and_match_oracle(width):
         assert np.array_equal(got[i], ref), (i, ws[i].n, ws[i].extra)
         assert np.array_equal(again[i], ref), i
         assert np.array_equal(solo[i], ref), i
+
+
+def test_layouts_give_the_same_integers_and_autotune_keeps_them():
+    """Every batch layout (class boundary, lanes per resident instance, wide
+    split class, tiled cells per lane and depth) computes the same integers;
+    the autotuner picks one of them, resets the instances and remembers it."""
+    ws = W.w4_batch(count=40, seed=21, smax=600)
+    ws += W.w4_tiled_mix(count=6, seed=22, nmin=1 << 10, nmax=1 << 17, smin=50, smax=200)
+    probs, q0s, ops = [], [], []
+    for w in ws:
+        lut = w.extra.get("lut", False)
+        probs.append(F.make_problem(w.kind, w.delta, w.lam, w.n, itype=F.I32, a=w.a,
+                                    eval_=F.EVAL_LUT if lut else F.EVAL_DIRECT))
+        q0s.append(O.quantise(w.u0, w.delta, 32))
+        ops.append(O.Problem(O.UPWIND if w.kind == W.UPWIND else O.BURGERS_EO, w.delta, w.lam,
+                             width=32, a=w.a))
+    steps = [w.steps for w in ws]
+    refs = [O.step(op, q0, s, omp=True) for op, q0, s in zip(ops, q0s, steps)]
+    layouts = [dict(), dict(class0_max_cells=8192, class0_lanes=128, wide_split_class=2),
+               dict(class0_lanes=256, tiled_vec=8, tiled_depth=48),
+               dict(class0_max_cells=16384, class0_lanes=512, wide_split_class=1, tiled_vec=4,
+                    tiled_depth=24)]
+    h = F.fqnm_batch_create(probs, [q.astype(np.int32) for q in q0s], steps)
+    try:
+        for lay in layouts:
+            F.fqnm_batch_set_config(h, **lay)
+            F.fqnm_batch_reset(h)
+            F.fqnm_batch_run(h)
+            for i, p in enumerate(probs):
+                assert np.array_equal(F.fqnm_batch_get_state(h, i, p).astype(np.int64),
+                                      refs[i]), (lay, i)
+        with pytest.raises(F.FqnmError):
+            F.fqnm_batch_set_config(h, class0_lanes=100)
+        cfg = F.fqnm_batch_autotune(h)
+        for i, p in enumerate(probs):  # reset to the initial states
+            assert np.array_equal(F.fqnm_batch_get_state(h, i, p).astype(np.int64), q0s[i])
+        F.fqnm_batch_run(h)
+        for i, p in enumerate(probs):
+            assert np.array_equal(F.fqnm_batch_get_state(h, i, p).astype(np.int64), refs[i])
+    finally:
+        F.fqnm_batch_destroy(h)
+    h2 = F.fqnm_batch_create(probs, [q.astype(np.int32) for q in q0s], steps)
+    try:
+        assert F.fqnm_batch_get_config(h2) == cfg  # remembered for batches of this shape
+    finally:
+        F.fqnm_batch_destroy(h2)
