@@ -110,7 +110,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, serve, levels, nd, euler")
+    ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, batch_only "
+                    "(the batched W4 run alone), serve, levels, nd, euler")
     return ap.parse_args()
 
 
@@ -253,6 +254,30 @@ def bench_batch(F, W, stream, G, reps=3):
                          "layout": {"autotuned": cfg, "autotune_s": t_tune,
                                     "default_layout_ms": t_default * 1e3},
                          "parity_vs_oracle": {"checked": checked, "bit_exact": ok}}}
+
+
+def bench_batch_only(F, W, stream, reps=2):
+    """The batched W4 run alone, in the default layout (a short command for
+    profilers: no autotuning and no per-instance loop)."""
+    import torch
+    ws = W.w4_batch()
+    sizes = [w.n for w in ws]
+    q_all = F.fqnm_quantise(np.concatenate([w.u0 for w in ws]), ws[0].delta, F.I32, stream)
+    q0s = np.split(q_all, np.cumsum(sizes)[:-1])
+    probs = [F.make_problem(w.kind, w.delta, w.lam, w.n, itype=F.I32, a=w.a) for w in ws]
+    h = F.fqnm_batch_create(probs, q0s, [w.steps for w in ws], stream)
+    try:
+        ts = []
+        for _ in range(reps):
+            F.fqnm_batch_reset(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F.fqnm_batch_run(h)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+    finally:
+        F.fqnm_batch_destroy(h)
+    return {"w4_batched_only": {"batched_ms": float(np.median(ts)) * 1e3}}
 
 
 def bench_tiled_mix(F, W, stream, reps=3):
@@ -689,6 +714,8 @@ def run_extras_only(args, F, W, plans, stream, G):
     elif args.only == "batch":
         extras.update(bench_batch(F, W, stream, G))
         extras.update(bench_tiled_mix(F, W, stream))
+    elif args.only == "batch_only":
+        extras.update(bench_batch_only(F, W, stream, reps=max(args.steps, 1)))
     elif args.only == "serve":
         extras.update(bench_serve(F, W, stream, G))
     elif args.only == "levels":

@@ -338,8 +338,13 @@ fqnm_status fqnm_step_transitions(fqnm_ctx* ctx, int64_t* from, int64_t* to, int
  * of their steps inside persistent launches with their state held in
  * registers: three kernels, one per size class, side by side on the caller's
  * stream and two library streams forked from it and joined back.  Other
- * instances use the single-grid stepper.  The whole run is captured once as a
- * HIP graph and replayed.
+ * instances (tables, 64-bit states, Lax-Friedrichs maps, larger grids) run
+ * as tiled work items: one launch per step block advances every such
+ * instance's tiles together, on a library stream beside the persistent
+ * kernels.  The whole run is captured once as a HIP graph and replayed (with
+ * the environment variable FQNM_BATCH_NO_GRAPH set when the batch is
+ * created, the same launches are issued directly instead, for profilers that
+ * cannot follow graph replays).
  * ---------------------------------------------------------------------- */
 typedef struct fqnm_batch fqnm_batch;
 

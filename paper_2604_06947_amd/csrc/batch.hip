@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -397,6 +398,7 @@ struct fqnm_batch {
   std::vector<int32_t> copy_back;  // tiled instances whose last block wrote buf1
   std::vector<BInst> res_base;     // resident instances, before the layout fills vec, cls
   fqnm_batch_config cfg{};         // current layout
+  bool direct = false;             // launches issued directly instead of a graph replay
   hipStream_t tstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<fqnm_ctx*> solo;   // per-instance comparison contexts (created on demand)
@@ -606,12 +608,12 @@ static bool lookup_batch_config(const std::string& key, fqnm_batch_config* out) 
   return true;
 }
 
-static fqnm_status batch_build_graph(fqnm_batch* b) {
-  B_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+// The launches of one batched run, on b->stream (the tiled instances on
+// their own stream, forked from it and joined back).
+static hipError_t batch_issue(fqnm_batch* b) {
   hipError_t e = hipSuccess;
-  fqnm_status st = FQNM_OK;
   const bool tiled = !b->tlaunch.empty() || !b->copy_back.empty();
-  if (tiled) {  // the tiled instances run on their own stream, forked and joined
+  if (tiled) {
     e = hipEventRecord(b->ev_fork, b->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->tstream, b->ev_fork, 0);
   }
@@ -631,10 +633,19 @@ static fqnm_status batch_build_graph(fqnm_batch* b) {
     e = hipEventRecord(b->ev_join, b->tstream);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join, 0);
   }
+  return e;
+}
+
+// Capture the run once into a graph (unless the batch issues its launches
+// directly, FQNM_BATCH_NO_GRAPH set at create: for profilers that cannot
+// follow graph replays).
+static fqnm_status batch_build_graph(fqnm_batch* b) {
+  if (b->direct) return FQNM_OK;
+  B_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  const hipError_t e = batch_issue(b);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); b->poisoned = true; return hip_fail(e, "batch launch"); }
-  if (st) { if (g) (void)hipGraphDestroy(g); b->poisoned = true; return st; }
   if (e2 != hipSuccess) { b->poisoned = true; return hip_fail(e2, "end capture"); }
   b->graph = g;
   B_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
@@ -652,6 +663,7 @@ fqnm_status fqnm_batch_create(const fqnm_problem* probs, const void* const* q0s,
   fqnm_batch* b = new fqnm_batch();
   b->user = static_cast<hipStream_t>(hip_stream);
   b->count = count;
+  b->direct = std::getenv("FQNM_BATCH_NO_GRAPH") != nullptr;
   b->probs.assign(probs, probs + count);
   b->steps.assign(steps, steps + count);
   // validate and lay out: every instance starts on a 16-byte boundary
@@ -749,7 +761,8 @@ fqnm_status fqnm_batch_run(fqnm_batch* b) {
   if (b->poisoned) return fail(FQNM_ERR_DEVICE, "batch is poisoned");
   B_HIP(hipEventRecord(b->ev_in, b->user), "record");
   B_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0), "wait");
-  B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
+  if (b->direct) B_HIP(batch_issue(b), "batch launch");
+  else B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
   B_HIP(hipEventRecord(b->ev_out, b->stream), "record");
   B_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0), "wait");
   return FQNM_OK;
@@ -821,7 +834,8 @@ fqnm_status fqnm_batch_autotune(fqnm_batch* b) {
       B_HIP(hipMemcpyAsync(b->d_state, b->d_init, es * b->total, hipMemcpyDeviceToDevice,
                            b->stream), "reset");
       B_HIP(hipEventRecord(e0, b->stream), "record");
-      B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
+      if (b->direct) B_HIP(batch_issue(b), "batch launch");
+      else B_HIP(hipGraphLaunch(b->exec, b->stream), "graph launch");
       B_HIP(hipEventRecord(e1, b->stream), "record");
       B_HIP(hipEventSynchronize(e1), "sync");
       float t = 0.f;

@@ -256,3 +256,24 @@ def test_layouts_give_the_same_integers_and_autotune_keeps_them():
         assert F.fqnm_batch_get_config(h2) == cfg  # remembered for batches of this shape
     finally:
         F.fqnm_batch_destroy(h2)
+
+
+def test_direct_launches_match_the_graph(monkeypatch):
+    """With FQNM_BATCH_NO_GRAPH set at create the batch issues its launches
+    directly instead of replaying the captured graph: the same integers."""
+    insts = [instance(k, n, 30 + k, [F.FLUX_UPWIND, F.FLUX_BURGERS_EO][k % 2], F.BC_PERIODIC,
+                      seed=5000 + k, lut=(k == 3)) for k, n in enumerate([300, 5000, 20000, 70001])]
+    probs = [p for p, _, _, _ in insts]
+    monkeypatch.setenv("FQNM_BATCH_NO_GRAPH", "1")
+    h = F.fqnm_batch_create(probs, [q.astype(np.int32) for _, q, _, _ in insts],
+                            [s for _, _, s, _ in insts])
+    monkeypatch.delenv("FQNM_BATCH_NO_GRAPH")
+    try:
+        for _ in range(2):
+            F.fqnm_batch_reset(h)
+            F.fqnm_batch_run(h)
+            for i, (p, q0, steps, op) in enumerate(insts):
+                assert np.array_equal(F.fqnm_batch_get_state(h, i, p).astype(np.int64),
+                                      O.step(op, q0, steps)), i
+    finally:
+        F.fqnm_batch_destroy(h)
