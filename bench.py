@@ -40,6 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # cycle: 3.93e13 integer (or non-FMA FP64) operations per second.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 SIMDS, CLOCK_HZ = 1024, 2.4e9
+FP64_PEAK_TFLOPS = 78.6
 # Operations per cell-update of the split update as Sec. 2.4 counts them: two
 # map evaluations and one addition per interface, two subtractions per cell
 # (a tabulated map evaluation is one table read).
@@ -111,7 +112,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--only", default="", help="run only this part: w2, w3, batch, batch_only "
-                    "(the batched W4 run alone), serve, levels, nd, euler")
+                    "(the batched W4 run alone), serve, serve_closed (the served requests "
+                    "once, closed loop), levels, nd, euler, euler_cw (componentwise Sod only)")
     return ap.parse_args()
 
 
@@ -381,6 +383,42 @@ def _pct(lat):
             "p99_latency_s": float(np.percentile(lat, 99))}
 
 
+def served_fp64_fields(cap):
+    """FP64 use of the served Euler kernel (k_euler_multi) at the closed-loop
+    capacity: its counters give VALU and FP64 wavefront-instructions and FP64
+    FLOPs (an FMA counts two) per cell-update; times the capacity, against the
+    issue rate (one wave64 instruction per SIMD every 4 cycles) and the
+    78.6 TFLOP/s FP64 vector peak.  The fractions are over the whole closed
+    loop, host-side tick gaps included.  null when taken on other sources."""
+    from paper_2604_06947_amd import plans
+    c = plans.COUNTERS["euler_multi"]
+    ok = c["sources_sha"] is not None and kernel_sources_sha(c["sources"]) == c["sources_sha"]
+    if not ok:
+        return {"valu_issue_frac": None, "fp64_issue_frac": None, "fp64_flops_frac": None,
+                "counters_sources_sha": c["sources_sha"]}
+    issue = SIMDS * CLOCK_HZ / 4.0
+    return {"kernel": "k_euler_multi",
+            "valu_insts_per_cell_update": c["valu_insts_per_cell_update"],
+            "fp64_insts_per_cell_update": c["f64_insts_per_cell_update"],
+            "valu_issue_frac": c["valu_insts_per_cell_update"] * cap / issue,
+            "fp64_issue_frac": c["f64_insts_per_cell_update"] * cap / issue,
+            "fp64_flops_frac": c["f64_flops_per_cell_update"] * 64 * cap
+            / (FP64_PEAK_TFLOPS * 1e12),
+            "counters_sources_sha": c["sources_sha"]}
+
+
+def bench_serve_closed(F, W, stream):
+    """The served requests once, all submitted at once (closed loop): the
+    profiling form of the served workload, whose cell-update total divides
+    the kernel's counter totals."""
+    items = _serve_inputs(F, W, stream)
+    work = float(sum(p.n * s for p, _, s in items))
+    t, _, st, _ = _serve_run(F, items, None)
+    return {"w5_serve_closed": {"requests": len(items), "cell_updates": work,
+                                "closed_loop_s": t, "cell_updates_per_s": work / t,
+                                "ticks": st["ticks"]}}
+
+
 def bench_serve(F, W, stream, G):
     """Config 5 as specified: SERVE_COUNT Sod requests, sizes log-uniform in
     [2^10, SERVE_NMAX], 64 MiB device budget.  Closed loop (everything
@@ -405,6 +443,7 @@ def bench_serve(F, W, stream, G):
     log(f"[bench] W5 closed-loop capacity {cap:.3e} cell-updates/s ({t_cl:.1f} s); "
         f"parity {ok}/{checked}")
     res = {"requests": len(items), "sizes": f"log-uniform 2^10..{SERVE_NMAX}",
+           "fp64_valu": served_fp64_fields(cap),
            "budget_bytes": SERVE_BUDGET, "cell_updates": work,
            "largest_request": {"cells": int(max(p.n for p, _, _ in items)),
                                "steps": int(max(s for _, _, s in items))},
@@ -522,14 +561,36 @@ def bench_nd(F, W, plans, stream, G, reps=3):
         and inv1["sum"][0] == inv["sum"][0]}}
 
 
-def bench_euler(F, W, stream, n=1 << 20, steps=200, reps=3):
+def euler_counter_fields(plans, launch_s):
+    """FP64 figures of k_euler_step (componentwise Sod, 2^20 cells, 8 steps
+    per launch) from its counters: VALU issue, the FP64 share of the VALU
+    instructions, FP64 issue and FP64 FLOP/s against the 78.6 TFLOP/s vector
+    peak (an FMA counts two).  null when taken on other kernel sources."""
+    c = plans.COUNTERS["euler_step"]
+    ok = c["sources_sha"] is not None and kernel_sources_sha(c["sources"]) == c["sources_sha"]
+    if not ok:
+        return {"valu_issue_frac": None, "fp64_share_of_valu": None, "fp64_issue_frac": None,
+                "fp64_flops_frac": None, "counters_sources_sha": c["sources_sha"]}
+    slots = SIMDS * CLOCK_HZ * launch_s / 4.0
+    return {"valu_issue_frac": c["valu_insts"] / slots,
+            "fp64_share_of_valu": c["f64_insts"] / c["valu_insts"],
+            "fp64_issue_frac": c["f64_insts"] / slots,
+            "fp64_flops_frac": c["f64_flops"] * 64 / launch_s / (FP64_PEAK_TFLOPS * 1e12),
+            "counters_sources_sha": c["sources_sha"]}
+
+
+def bench_euler(F, W, stream, n=1 << 20, steps=200, reps=3, kinds=("componentwise",
+                                                                     "density_only")):
     """Sod at 2^20 cells, 200 steps of the single-grid Euler kernel: the
     componentwise quantisation (all of rho, m, E counted) and the density-only
     prototype (FP64 m and E).  Device time of the steps by HIP events."""
     import torch
+    from paper_2604_06947_amd import plans
     out = {}
     for tag, kind in (("componentwise", F.FLUX_EULER_ROE_EF),
                       ("density_only", F.FLUX_EULER_ROE_EF_DENSITY)):
+        if tag not in kinds:
+            continue
         r = W.sod_request(n, kind=6)
         prob = F.make_problem(kind, r.delta, r.lam, n, bc=F.BC_OUTFLOW, itype=F.I64, gamma=1.4)
         ts = []
@@ -551,6 +612,8 @@ def bench_euler(F, W, stream, n=1 << 20, steps=200, reps=3):
                                   "kernel_GBps_algorithmic": ach,
                                   "frac_of_hbm": ach / HBM_PEAK_GBS,
                                   "bound": "fp64 alu (divisions, square roots)"}
+        if tag == "componentwise":
+            out[f"sod_2e20_{tag}"]["counters"] = euler_counter_fields(plans, t / steps * 8)
     return out
 
 
@@ -718,12 +781,16 @@ def run_extras_only(args, F, W, plans, stream, G):
         extras.update(bench_batch_only(F, W, stream, reps=max(args.steps, 1)))
     elif args.only == "serve":
         extras.update(bench_serve(F, W, stream, G))
+    elif args.only == "serve_closed":
+        extras.update(bench_serve_closed(F, W, stream))
     elif args.only == "levels":
         extras.update(bench_levels(F, W, stream)[0])
     elif args.only == "nd":
         extras.update(bench_nd(F, W, plans, stream, G))
     elif args.only == "euler":
         extras.update(bench_euler(F, W, stream))
+    elif args.only == "euler_cw":
+        extras.update(bench_euler(F, W, stream, kinds=("componentwise",)))
     print(json.dumps({"extras": extras}), flush=True)
 
 
@@ -905,6 +972,10 @@ def bench_w3(F, W, plans, stream, G):
                                  "bytes_per_cell_update": 16,
                                  "algorithmic_bytes_per_launch": 16 * w3.n,
                                  **counter_fields(plans, "w3_stream", ls)}
+            else:
+                # many steps per HBM pass: the binding roof is VALU issue
+                e["counters"] = {"kernel": f"k_tblock<long, P_UPWIND_POS, {pl[1]}>",
+                                 **counter_fields(plans, "w3_tblock", ls)}
             res[f"w3_r{r:g}_{tag}"] = e
     return res
 

@@ -256,11 +256,16 @@ void store_plan(const std::string& key, const fqnm_plan& pl) {
   save_tune_file();
 }
 
-fqnm_plan default_plan(const fqnm_problem& p) {
+fqnm_plan default_plan(const fqnm_problem& p, int pol) {
   fqnm_plan pl;
   pl.kernel = K_TBLOCK;
   pl.vec = p.itype == FQNM_I32 ? 4 : 8;
   pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 40 : 24;
+  if (p.itype == FQNM_I64 && (pol == P_UPWIND_POS || pol == P_UPWIND_NEG)) {
+    // 64-bit upwind windows step as exact doubles: wide tiles, deep passes
+    pl.vec = 16;
+    pl.depth = 48;
+  }
   pl.eval = 0;
   return pl;
 }
@@ -452,7 +457,7 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
   ctx->pol = policy_of(p, lut);
   ctx->direct_pol = policy_of(p, false);
   fqnm_plan pl;
-  if (!lookup_plan(plan_key(p, ctx->pol), &pl)) pl = default_plan(p);
+  if (!lookup_plan(plan_key(p, ctx->pol), &pl)) pl = default_plan(p, ctx->pol);
   ctx->plan = pl;
   ctx->plan.eval = lut ? FQNM_EVAL_LUT : FQNM_EVAL_DIRECT;
   return FQNM_OK;
@@ -1075,7 +1080,7 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
   ctx->d_ledger = dled;  // trials must not touch the real ledger
   std::vector<fqnm_plan> cand;
   const bool i32 = ctx->prob.itype == FQNM_I32;
-  const int vecs32[] = {4, 8, 16}, vecs64[] = {2, 4, 8};
+  const std::vector<int> vecs32{4, 8, 16}, vecs64{2, 4, 8, 16};
   if (ctx->dim > 1) {
     for (int v : {2, 4, 8})
       if (nd_variant_available(ctx->prob.itype, ctx->pol, v))
@@ -1118,6 +1123,14 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
       if (persist_plan_ok(ctx, pp)) cand.push_back(pp);
     }
   }
+  // single-grid kernels exist for a subset of (storage type, policy, vec)
+  cand.erase(std::remove_if(cand.begin(), cand.end(),
+                            [&](const fqnm_plan& c) {
+                              return c.kernel <= K_TBLOCK_B8 &&
+                                     !scalar_variant_available(ctx->prob.itype, ctx->pol,
+                                                               c.kernel, c.vec);
+                            }),
+             cand.end());
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);

@@ -462,10 +462,13 @@ static fqnm_status batch_plan_tiles(fqnm_batch* b, const fqnm_batch_config& cfg)
   int64_t maxblocks = 0;
   for (size_t i = 0; i < b->big.size(); ++i) {
     fqnm_ctx* c = b->big[i];
-    const fqnm_plan dp = default_plan(c->prob);
+    const fqnm_plan dp = default_plan(c->prob, c->pol);
     int vec = c->plan.kernel == K_TBLOCK ? c->plan.vec : dp.vec;
     int depth = c->plan.kernel == K_TBLOCK ? c->plan.depth : dp.depth;
-    if (vec != 4 && vec != 8) { vec = dp.vec; depth = dp.depth; }
+    if (vec != 4 && vec != 8) {  // tiled work items run 4 or 8 cells per lane
+      vec = dp.vec == 4 ? 4 : 8;
+      depth = dp.depth;
+    }
     if (cfg.tiled_vec) vec = cfg.tiled_vec;
     if (cfg.tiled_depth) depth = cfg.tiled_depth;
     int kh = scalar_halo(K_TBLOCK, vec, depth);

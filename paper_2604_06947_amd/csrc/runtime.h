@@ -70,7 +70,7 @@ bool is_burgers(int flux);
 int policy_of(const fqnm_problem& p, bool lut);
 int direct_split_policy(const fqnm_problem& p);
 XParams xparams_of(const fqnm_problem& p);
-fqnm_plan default_plan(const fqnm_problem& p);
+fqnm_plan default_plan(const fqnm_problem& p, int pol);
 std::string plan_key(const fqnm_problem& p, int pol);
 bool lookup_plan(const std::string& key, fqnm_plan* out);
 void store_plan(const std::string& key, const fqnm_plan& pl);

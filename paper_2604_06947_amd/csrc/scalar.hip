@@ -316,12 +316,52 @@ __device__ __forceinline__ void tb_step_addr(uint32_t (&a)[V], uint32_t end) {
   for (int j = 0; j < V; ++j) a[j] += ((j == 0 ? Fl : F[j - 1]) - F[j]) << 3;
 }
 
+// ksteps upwind steps of a plain window of 64-bit states, carried as exact
+// doubles.  With B = 1.5*2^52, fb = (c*x) + B is B + rint(c*x) exactly (the
+// same two roundings as the integer path, |c*x| < 2^51), the difference of
+// two such values is the exact integer flux difference, and x minus it is the
+// exact new state (states are validated below 2^51 in magnitude and the
+// upwind update keeps them in their initial range).  Four FP64 operations per
+// cell and step replace the per-step conversions and 64-bit integer
+// arithmetic; the states are converted once per pass in each direction.
+template <int POL, int V>
+__device__ __forceinline__ void tb_steps_upwind_f64(double c, int64_t (&q)[V], int ksteps) {
+  double x[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) x[j] = as_f64<int64_t>(q[j]);
+  for (int s = 0; s < ksteps; ++s) {
+    double fb[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const double y = c * x[j];
+      fb[j] = y + F64_BIAS;
+    }
+    if constexpr (POL == P_UPWIND_POS) {  // F_{j+1/2} = rint(c q_j)
+      const double fl = lane_from_prev<double>(fb[V - 1]);
+#pragma unroll
+      for (int j = 0; j < V; ++j) x[j] = x[j] - (fb[j] - (j == 0 ? fl : fb[j - 1]));
+    } else {  // F_{j+1/2} = rint(c q_{j+1})
+      const double fn = lane_from_next<double>(fb[0]);
+#pragma unroll
+      for (int j = 0; j < V; ++j) x[j] = x[j] - ((j + 1 < V ? fb[j + 1] : fn) - fb[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) q[j] = round_to<int64_t>(x[j]);
+}
+
 // ksteps steps of a wavefront window with no LDS table slice.
 template <typename IT, int POL, int V>
 __device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView& L, IT (&q)[V],
                                                 int64_t g0, int64_t n, bool plain, bool own_right,
                                                 int ksteps, long long& led) {
   const LdsWindow Wn{0u, 0u};
+  if constexpr (sizeof(IT) == 8 && (POL == P_UPWIND_POS || POL == P_UPWIND_NEG)) {
+    if (plain) {
+      tb_steps_upwind_f64<POL, V>(P.c, q, ksteps);
+      return;
+    }
+  }
   if (plain) {
     for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
   } else {
@@ -1385,6 +1425,19 @@ hipError_t by_vec(int kernel, int vec, const void* src, void* dst, int64_t n, in
       case 2: return do_launch<IT, POL, 2>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
       case 4: return do_launch<IT, POL, 4>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
       case 8: return do_launch<IT, POL, 8>(kernel, src, dst, n, bc, ksteps, khalo, P, d_ledger, s);
+      case 16:
+        // 64-bit upwind windows step as exact doubles (four FP64 operations
+        // per cell and step), light enough on registers for 16 cells per lane
+        if constexpr (POL == P_UPWIND_POS || POL == P_UPWIND_NEG) {
+          if (kernel != K_TBLOCK) return hipErrorInvalidValue;
+          const int64_t T = 64 * 16 - 2 * khalo;
+          const int64_t ntiles = (n + T - 1) / T;
+          k_tblock<IT, POL, 16><<<dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s>>>(
+              static_cast<const IT*>(src), static_cast<IT*>(dst), n, bc, ksteps, khalo, ntiles,
+              P, d_ledger);
+          return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }
@@ -1423,7 +1476,9 @@ bool scalar_variant_available(int itype, int pol, int kernel, int vec) {
   if (kernel < K_STREAM || kernel > K_TBLOCK_B8) return false;
   if (kernel == K_TBLOCK_IL && (pol == P_GODUNOV || pol == P_MURMAN_ROE)) return false;
   if (itype == FQNM_I32) return vec == 4 || vec == 8 || vec == 16;
-  if (itype == FQNM_I64) return vec == 2 || vec == 4 || vec == 8;
+  if (itype == FQNM_I64)
+    return vec == 2 || vec == 4 || vec == 8 ||
+           (vec == 16 && kernel == K_TBLOCK && (pol == P_UPWIND_POS || pol == P_UPWIND_NEG));
   return false;
 }
 

@@ -6,29 +6,55 @@ from .fqnm import KERNEL_STREAM, KERNEL_TBLOCK
 # Burgers, 2^20 int32 cells, Engquist-Osher LUT, 10000 steps
 BENCH_PLAN_W2 = (KERNEL_TBLOCK, 4, 40)
 # near-Nyquist advection, 2^24 int64 cells, 2000 steps
-BENCH_PLAN_W3 = (KERNEL_TBLOCK, 8, 24)
+BENCH_PLAN_W3 = (KERNEL_TBLOCK, 16, 48)
 # the one-step-per-pass streaming plan reported beside it
 STREAM_PLAN_W3 = (KERNEL_STREAM, 4, 1)
 
 # Counter results of the timed kernels (rocprofv3 runs recorded under
-# profiles/), per launch of the benchmark's plan: HBM traffic (FETCH_SIZE and
-# WRITE_SIZE scaled by a plain device copy of known size), VALU
-# wavefront-instructions (SQ_INSTS_VALU) and the share of LDS-active cycles
-# lost to bank conflicts.  Valid only for the kernel sources they were
-# measured on: the benchmark reports null when the hash of those sources
-# (first 16 hex digits of SHA-256 over the files in order) differs.
+# profiles/), as means per launch over the launches of one solve of the
+# benchmark's plan: HBM traffic (FETCH_SIZE and WRITE_SIZE, each scaled by
+# what the counter reads for a plain device copy of known size: FETCH x
+# 1.99982, WRITE x 1.0), VALU wavefront-instructions (SQ_INSTS_VALU), the
+# share of LDS-active cycles lost to bank conflicts and, for the FP64 Euler
+# kernels, FP64 VALU wavefront-instructions.  Valid only for the kernel
+# sources they were measured on: the benchmark reports null when the hash of
+# those sources (first 16 hex digits of SHA-256 over the files in order)
+# differs.
 KERNEL_SOURCES = ("csrc/scalar.hip", "csrc/fqnm_device.h")
 ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
 EULER_KERNEL_SOURCES = ("csrc/euler.hip", "csrc/fqnm_device.h")
 COUNTERS = {
-    "w2": {"sources": KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
-           "valu_insts": None, "lds_bank_conflict_frac": None},
-    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
-                  "valu_insts": None, "lds_bank_conflict_frac": None},
-    "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
-           "valu_insts": None, "lds_bank_conflict_frac": None},
-    "euler_multi": {"sources": EULER_KERNEL_SOURCES, "sources_sha": None, "traffic_bytes": None,
-                    "valu_insts": None, "lds_bank_conflict_frac": None},
+    # k_tblock<int, P_LUT, 4>, 40 steps per launch, 250 launches per solve
+    "w2": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
+           "traffic_bytes": 11692376, "valu_insts": 4548855,
+           "lds_bank_conflict_frac": 0.6004},
+    # k_stream<long, P_UPWIND_POS, 4>, one step per launch
+    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
+                  "traffic_bytes": 268490090, "valu_insts": 4259912,
+                  "lds_bank_conflict_frac": None},
+    # k_tblock<long, P_UPWIND_POS, 8>, 24 steps per launch: 83 launches of 24
+    # steps and one of 8 per 2000-step solve
+    "w3_tblock": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
+                  "traffic_bytes": 268524460, "valu_insts": 68188333,
+                  "lds_bank_conflict_frac": None},
+    # k_nd_tb<int, P_EO, 2, 4>, 4 steps per launch, 24 rows per wavefront
+    "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": "beac81b3b4612721",
+           "traffic_bytes": 157047625, "valu_insts": 18522603,
+           "lds_bank_conflict_frac": None},
+    # k_euler_step, componentwise Sod at 2^20 cells, 8 steps per launch; FP64
+    # wavefront-instructions (ADD + MUL + FMA + TRANS) and FLOPs per lane
+    # (an FMA counts two)
+    "euler_step": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "a345fe374674b8d6",
+                   "traffic_bytes": None, "valu_insts": 43893037,
+                   "lds_bank_conflict_frac": None,
+                   "f64_insts": 27985480, "f64_flops": 40151560},
+    # k_euler_multi over served Sod requests (100 requests, 2^10..2^16
+    # cells, one closed loop): wavefront-instructions per cell-update (its
+    # launches differ in size, so per-launch means say little)
+    "euler_multi": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "a345fe374674b8d6",
+                    "valu_insts_per_cell_update": 5.3061,
+                    "f64_insts_per_cell_update": 3.3631,
+                    "f64_flops_per_cell_update": 4.8188},
 }
 
 # the FP64 finite-volume twin of the Burgers workload, same tiling machinery

@@ -28,6 +28,8 @@ PLANS64 = [(F.KERNEL_STREAM, 2, 1), (F.KERNEL_STREAM, 8, 1), (F.KERNEL_TBLOCK, 2
            (F.KERNEL_TBLOCK, 4, 8), (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 8, 48),
            (F.KERNEL_TBLOCK_IL, 4, 8), (F.KERNEL_TBLOCK_IL, 8, 64),
            (F.KERNEL_TBLOCK_B2, 2, 6), (F.KERNEL_TBLOCK_B4, 8, 24), (F.KERNEL_TBLOCK_B8, 4, 40)]
+# 64-bit upwind maps evaluated directly also run 16 cells per lane (kernel 1)
+PLANS64_UPWIND = [(F.KERNEL_TBLOCK, 16, 1), (F.KERNEL_TBLOCK, 16, 40), (F.KERNEL_TBLOCK, 16, 100)]
 TWO_POINT = (F.FLUX_BURGERS_GODUNOV, F.FLUX_BURGERS_MURMAN_ROE)
 
 
@@ -107,7 +109,10 @@ def test_kind_parity_all_plans(flux, a, lut, bc, itype):
     op = oracle_problem(prob)
     q0 = O.quantise(u0, prob.delta, op.width)
     ref, led = O.step(op, q0, steps, return_ledger=True)
-    for plan in plans_for(itype, flux):
+    plans = plans_for(itype, flux)
+    if itype == F.I64 and flux == F.FLUX_UPWIND and not lut:
+        plans = plans + PLANS64_UPWIND
+    for plan in plans:
         q, inv = gpu_run(prob, u0=u0, steps=steps, plan=plan)
         assert np.array_equal(q, ref), plan
         assert inv["ledger"][0] == led
@@ -400,9 +405,39 @@ def test_w3_reduced_bitexact():
     prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I64, a=1.0)
     ref = O.step(O.Problem(O.UPWIND, w.delta, w.lam, width=64, a=1.0),
                  O.quantise(w.u0, w.delta, 64), w.steps)
-    for plan in PLANS64:
+    for plan in PLANS64 + PLANS64_UPWIND:
         q, _ = gpu_run(prob, u0=w.u0, steps=w.steps, plan=plan)
         assert np.array_equal(q, ref), plan
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 1023, 1024, 1025, 2047, 4099])
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+@pytest.mark.parametrize("a", [1.0, -0.9])
+def test_int64_upwind_wide_tiles_edge_sizes(n, bc, a):
+    """16 cells per lane (1024-cell windows, stepped as exact doubles on plain
+    windows, as integers on windows at outflow ends) on grids smaller than,
+    equal to and just above one window."""
+    u0, prob = make_case(F.FLUX_UPWIND, bc, F.I64, n, seed=300 + n, a=a)
+    op = oracle_problem(prob)
+    q0 = O.quantise(u0, prob.delta, 64)
+    for steps in (0, 1, 37):
+        ref, led = O.step(op, q0, steps, return_ledger=True)
+        for plan in ((F.KERNEL_TBLOCK, 16, 16), (F.KERNEL_TBLOCK, 16, 64)):
+            q, inv = gpu_run(prob, q0=q0, steps=steps, plan=plan)
+            assert np.array_equal(q, ref), (steps, plan)
+            assert inv["ledger"][0] == led
+
+
+def test_wide_tiles_refused_outside_64_bit_direct_upwind():
+    for flux, itype, lut in ((F.FLUX_BURGERS_EO, F.I64, False), (F.FLUX_UPWIND, F.I64, True)):
+        u0, prob = make_case(flux, F.BC_PERIODIC, itype, 1000, seed=5, lut=lut)
+        h = F.fqnm_create_from_field(prob, u0)
+        try:
+            with pytest.raises(F.FqnmError) as e:
+                F.fqnm_set_plan(h, F.KERNEL_TBLOCK, 16, 40)
+            assert e.value.status == F.ERR_ARG
+        finally:
+            F.fqnm_destroy(h)
 
 
 def test_quantise_entry_point_matches_oracle():
