@@ -431,6 +431,7 @@ def bench_serve(F, W, stream, G):
     items = _serve_inputs(F, W, stream)
     work_of = np.array([float(p.n * s) for p, _, s in items])
     work = float(work_of.sum())
+    big = int(np.argmax([p.n for p, _, _ in items]))
     t_cl, lat_cl, st_cl, outs = _serve_run(F, items, None)
     cap = work / t_cl
     checked = ok = 0
@@ -445,8 +446,7 @@ def bench_serve(F, W, stream, G):
     res = {"requests": len(items), "sizes": f"log-uniform 2^10..{SERVE_NMAX}",
            "fp64_valu": served_fp64_fields(cap),
            "budget_bytes": SERVE_BUDGET, "cell_updates": work,
-           "largest_request": {"cells": int(max(p.n for p, _, _ in items)),
-                               "steps": int(max(s for _, _, s in items))},
+           "largest_request": {"cells": int(items[big][0].n), "steps": int(items[big][2])},
            "closed_loop_cell_updates_per_s": cap, "closed_loop_s": t_cl,
            "closed_loop_p50_s": float(np.percentile(lat_cl, 50)),
            "closed_loop_p99_s": float(np.percentile(lat_cl, 99)),

@@ -25,17 +25,17 @@ ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
 EULER_KERNEL_SOURCES = ("csrc/euler.hip", "csrc/fqnm_device.h")
 COUNTERS = {
     # k_tblock<int, P_LUT, 4>, 40 steps per launch, 250 launches per solve
-    "w2": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
-           "traffic_bytes": 11692376, "valu_insts": 4548855,
-           "lds_bank_conflict_frac": 0.6004},
+    "w2": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
+           "traffic_bytes": 11670790, "valu_insts": 4548855,
+           "lds_bank_conflict_frac": 0.6000},
     # k_stream<long, P_UPWIND_POS, 4>, one step per launch
-    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
-                  "traffic_bytes": 268490090, "valu_insts": 4259912,
+    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
+                  "traffic_bytes": 268491266, "valu_insts": 4259912,
                   "lds_bank_conflict_frac": None},
-    # k_tblock<long, P_UPWIND_POS, 8>, 24 steps per launch: 83 launches of 24
-    # steps and one of 8 per 2000-step solve
-    "w3_tblock": {"sources": KERNEL_SOURCES, "sources_sha": "3124d2203667fd05",
-                  "traffic_bytes": 268524460, "valu_insts": 68188333,
+    # k_tblock<long, P_UPWIND_POS, 16>, 48 steps per launch: 41 launches of
+    # 48 steps and one of 32 per 2000-step solve
+    "w3_tblock": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
+                  "traffic_bytes": 268561685, "valu_insts": 60318516,
                   "lds_bank_conflict_frac": None},
     # k_nd_tb<int, P_EO, 2, 4>, 4 steps per launch, 24 rows per wavefront
     "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": "beac81b3b4612721",
