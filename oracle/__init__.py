@@ -7,10 +7,12 @@ here imports the product package.
 
 Contents
 --------
-* ``fqnm_oracle.c`` -- single-threaded C reference stepper (quantisation, the
-  transfer maps of every flux kind, the Jacobi integer update, invariants, the
-  FP64 classical comparators, the Euler/Roe transfer and level statistics).
-  Compiled with gcc, contraction off, by :func:`build`.
+* ``fqnm_oracle.c`` -- C reference stepper (quantisation, the transfer maps
+  of every flux kind, the Jacobi integer update, invariants, the FP64
+  classical comparators, the Euler/Roe transfer and level statistics).
+  Compiled with gcc, contraction off, by :func:`build`: once plain
+  (single-threaded) and once with OpenMP (the same integers; for the
+  full-size digests and the all-cores CPU baseline).
 * :mod:`oracle.exact` -- exact solutions used as independent references
   (exact shift, Hopf-Lax/Lax-Oleinik for Burgers, exact Riemann solver).
 

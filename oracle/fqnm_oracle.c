@@ -1,8 +1,8 @@
 /*
  * fqnm_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded CPU reference for the Fast Quantised
- * Numerical Method (FQNM, arXiv 2604.06947).  Only the test-suite, the smoke
+ * A plain, slow CPU reference for the Fast Quantised Numerical Method (FQNM,
+ * arXiv 2604.06947).  Only the test-suite, the smoke
  * check and the CPU-baseline leg of the benchmark may load this library; the
  * product path (the HIP library and its Python binding) never does.  It shares
  * no code, header or constant table with the HIP implementation: both are
@@ -11,7 +11,11 @@
  *
  * Build: gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
  * (contraction off: every floating-point operation below is one IEEE op, in
- * the order written).  States are held in int64 regardless of the problem's
+ * the order written).  The same source also builds with -fopenmp: the
+ * stepping loops run over cells or interfaces that read only the state
+ * before the step, so the threads split independent work and both builds give
+ * the same integers (tested); the threaded build serves the full-size
+ * digests and the all-cores CPU baseline.  States are held in int64 regardless of the problem's
  * storage width; for 32-bit problems every intermediate integer is checked to
  * lie in the int32 range so that a 32-bit implementation computes the same
  * numbers.
