@@ -447,12 +447,21 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
     const size_t eb = p.itype == FQNM_I32 ? 8 : 16;
     if (!ctx_dmalloc(ctx, &ctx->d_lut, eb * count))
       return fail(FQNM_ERR_OOM, "allocation of the LUT failed");
+    // the reduction partials (free again after ctx_minmax) hold the
+    // certificate's violation flag
+    int* viol = reinterpret_cast<int*>(ctx->d_red);
+    CTX_HIP(hipMemsetAsync(viol, 0, sizeof(int), ctx->stream), "flag reset");
     CTX_HIP(launch_lut_build(p.itype, direct_split_policy(p), ctx->xp, ctx->d_lut, lo, count,
-                             ctx->stream), "LUT build");
+                             viol, ctx->stream), "LUT build");
+    int violated = 1;
+    CTX_HIP(hipMemcpyAsync(&violated, viol, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+            "copy flag");
+    CTX_HIP(hipStreamSynchronize(ctx->stream), "sync");
     ctx->xp.lut = ctx->d_lut;
     ctx->xp.lut_lo = lo;
     ctx->xp.lut_last = count - 1;
     ctx->xp.lut_pol = direct_split_policy(p);
+    ctx->xp.lut_mono = violated ? 0 : 1;
   }
   ctx->pol = policy_of(p, lut);
   ctx->direct_pol = policy_of(p, false);

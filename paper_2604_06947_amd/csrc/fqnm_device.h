@@ -39,6 +39,7 @@ struct XParams {
   int64_t lut_lo;   // first tabulated state
   int64_t lut_last; // number of entries - 1
   int32_t lut_pol;  // P_LUT: the direct split policy whose maps the table holds
+  int32_t lut_mono; // P_LUT: 1 when the table certifies the maximum principle (k_lut_build)
 };
 
 // For 64-bit states the conversions use the bias B = 1.5*2^52: for |v| < 2^51

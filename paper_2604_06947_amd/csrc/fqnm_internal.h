@@ -132,7 +132,7 @@ hipError_t launch_nd_tb(int itype, int pol, int vec, int depth, int rows, const 
                         void* dst, const NdParams& P, long long* d_ledger, hipStream_t s);
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
-                            int64_t count, hipStream_t s);
+                            int64_t count, int* violation, hipStream_t s);
 hipError_t launch_quantise(int itype, const double* u, void* q, int64_t n, double delta,
                            int* d_err, hipStream_t s);
 hipError_t launch_reconstruct(int itype, const void* q, double* u, int64_t n, double delta,

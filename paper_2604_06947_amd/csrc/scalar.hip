@@ -350,6 +350,38 @@ __device__ __forceinline__ void tb_steps_upwind_f64(double c, int64_t (&q)[V], i
   for (int j = 0; j < V; ++j) q[j] = round_to<int64_t>(x[j]);
 }
 
+// The same step for a table that certifies the maximum principle (XParams
+// lut_mono): the window's first and last cells stay frozen, so every other
+// cell's update is the certified monotone function of three states of the
+// slice and stays in it, and no read needs a clamp.  The frozen cells are
+// halo; they take the place of the wrong values the zero-filled end moves
+// give the ends, and reach the stored interior no sooner.  keep_first and
+// keep_last are all-ones except in the wavefront's first and last lane
+// (zero there); masking the two end cells' flux differences with them costs
+// one instruction each, where the clamps cost one per cell.
+template <int V>
+__device__ __forceinline__ void tb_step_addr_frozen(uint32_t (&a)[V], uint32_t keep_first,
+                                                    uint32_t keep_last) {
+  uint32_t pp[V], pm[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const uint64_t e = *(lds_u64*)(static_cast<uintptr_t>(a[j]));
+    pp[j] = static_cast<uint32_t>(e);
+    pm[j] = static_cast<uint32_t>(e >> 32);
+  }
+  uint32_t F[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) F[j] = (j + 1 < V ? pm[j + 1] : tb_from_next_z(pm[0])) + pp[j];
+  const uint32_t Fl = tb_from_prev_z(F[V - 1]);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    uint32_t d = (j == 0 ? Fl : F[j - 1]) - F[j];
+    if (j == 0) d &= keep_first;
+    if (j == V - 1) d &= keep_last;
+    a[j] += d << 3;
+  }
+}
+
 // ksteps steps of a wavefront window with no LDS table slice.
 template <typename IT, int POL, int V>
 __device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView& L, IT (&q)[V],
@@ -435,7 +467,14 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
 #pragma unroll
         for (int j = 0; j < V; ++j)
           a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(mn)) << 3);
-        for (int s = 0; s < ksteps; ++s) tb_step_addr<V>(a, end);
+        if (P.lut_mono) {
+          // masks made by the zero-filling end moves, so that the compiler
+          // keeps them as masks rather than turning them into selects
+          const uint32_t keep_first = tb_from_prev_z(~0u), keep_last = tb_from_next_z(~0u);
+          for (int s = 0; s < ksteps; ++s) tb_step_addr_frozen<V>(a, keep_first, keep_last);
+        } else {
+          for (int s = 0; s < ksteps; ++s) tb_step_addr<V>(a, end);
+        }
 #pragma unroll
         for (int j = 0; j < V; ++j)
           q[j] = static_cast<IT>(static_cast<uint32_t>(mn) +
@@ -1222,9 +1261,17 @@ __global__ __launch_bounds__(256) void k_tblock_il(const IT* __restrict__ src,
 // ---------------------------------------------------------------------------
 // Off-loop kernels: LUT construction, quantisation, reconstruction, reduction.
 // ---------------------------------------------------------------------------
+// Builds the table {phi+(q), phi-(q)} for q in [lo, lo + count) and checks, for
+// every pair of consecutive states, that phi+ does not decrease, phi- does not
+// increase and g(q) = q - phi+(q) + phi-(q) does not decrease.  Then the
+// update H(a, b, c) = g(b) + phi+(a) - phi-(c) of a cell b between a and c is
+// non-decreasing in each argument and H(x, x, x) = x, so it lies between the
+// least and the largest of a, b, c: the maximum principle holds exactly, for
+// any three states of the table's range (Lemma cfl_monotone, checked on the
+// rounded maps themselves).  A violation sets *violation to 1.
 template <typename IT, int POL>
 __global__ void k_lut_build(XParams P, typename LutEntry<IT>::T* __restrict__ lut, int64_t lo,
-                            int64_t count) {
+                            int64_t count, int* __restrict__ violation) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
     IT q = static_cast<IT>(lo + i);
@@ -1232,6 +1279,13 @@ __global__ void k_lut_build(XParams P, typename LutEntry<IT>::T* __restrict__ lu
     e.x = split_phi<IT, POL>(P, q, true);
     e.y = split_phi<IT, POL>(P, q, false);
     lut[i] = e;
+    if (i + 1 < count) {
+      const IT q1 = static_cast<IT>(lo + i + 1);
+      const int64_t p0 = e.x, m0 = e.y;
+      const int64_t p1 = split_phi<IT, POL>(P, q1, true);
+      const int64_t m1 = split_phi<IT, POL>(P, q1, false);
+      if (p1 < p0 || m1 > m0 || 1 - (p1 - p0) + (m1 - m0) < 0) *violation = 1;
+    }
   }
 }
 
@@ -1664,12 +1718,12 @@ hipError_t launch_tblock_wg(int nw, int vec, const int32_t* src, int32_t* dst, i
 }
 
 hipError_t launch_lut_build(int itype, int pol, const XParams& P, void* lut, int64_t lo,
-                            int64_t count, hipStream_t s) {
+                            int64_t count, int* violation, hipStream_t s) {
   const unsigned g = grid_for(count, 256);
 #define FQNM_LUT_CASE(IT, p)                                                                 \
   case p:                                                                                    \
     k_lut_build<IT, p><<<g, 256, 0, s>>>(P, static_cast<typename LutEntry<IT>::T*>(lut), lo, \
-                                         count);                                             \
+                                         count, violation);                                  \
     return hipGetLastError();
   if (itype == FQNM_I32) {
     switch (pol) {

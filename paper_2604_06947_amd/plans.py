@@ -25,33 +25,33 @@ ND_KERNEL_SOURCES = ("csrc/nd_tb.hip", "csrc/nd_common.h", "csrc/fqnm_device.h")
 EULER_KERNEL_SOURCES = ("csrc/euler.hip", "csrc/fqnm_device.h")
 COUNTERS = {
     # k_tblock<int, P_LUT, 4>, 40 steps per launch, 250 launches per solve
-    "w2": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
-           "traffic_bytes": 11670790, "valu_insts": 4548855,
-           "lds_bank_conflict_frac": 0.6000},
+    "w2": {"sources": KERNEL_SOURCES, "sources_sha": "2544e8f6baab98cb",
+           "traffic_bytes": 11692242, "valu_insts": 4150084,
+           "lds_bank_conflict_frac": 0.5184},
     # k_stream<long, P_UPWIND_POS, 4>, one step per launch
-    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
-                  "traffic_bytes": 268491266, "valu_insts": 4259912,
+    "w3_stream": {"sources": KERNEL_SOURCES, "sources_sha": "2544e8f6baab98cb",
+                  "traffic_bytes": 268484381, "valu_insts": 4259912,
                   "lds_bank_conflict_frac": None},
     # k_tblock<long, P_UPWIND_POS, 16>, 48 steps per launch: 41 launches of
     # 48 steps and one of 32 per 2000-step solve
-    "w3_tblock": {"sources": KERNEL_SOURCES, "sources_sha": "ddba587fea144903",
-                  "traffic_bytes": 268561685, "valu_insts": 60318516,
+    "w3_tblock": {"sources": KERNEL_SOURCES, "sources_sha": "2544e8f6baab98cb",
+                  "traffic_bytes": 268572754, "valu_insts": 60318516,
                   "lds_bank_conflict_frac": None},
     # k_nd_tb<int, P_EO, 2, 4>, 4 steps per launch, 24 rows per wavefront
-    "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": "beac81b3b4612721",
-           "traffic_bytes": 157047625, "valu_insts": 18522603,
+    "w6": {"sources": ND_KERNEL_SOURCES, "sources_sha": "0f0e3440c669dd13",
+           "traffic_bytes": 157065418, "valu_insts": 18522603,
            "lds_bank_conflict_frac": None},
     # k_euler_step, componentwise Sod at 2^20 cells, 8 steps per launch; FP64
     # wavefront-instructions (ADD + MUL + FMA + TRANS) and FLOPs per lane
     # (an FMA counts two)
-    "euler_step": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "a345fe374674b8d6",
+    "euler_step": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "bcab913dbf5b785a",
                    "traffic_bytes": None, "valu_insts": 43893037,
                    "lds_bank_conflict_frac": None,
                    "f64_insts": 27985480, "f64_flops": 40151560},
     # k_euler_multi over served Sod requests (100 requests, 2^10..2^16
     # cells, one closed loop): wavefront-instructions per cell-update (its
     # launches differ in size, so per-launch means say little)
-    "euler_multi": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "a345fe374674b8d6",
+    "euler_multi": {"sources": EULER_KERNEL_SOURCES, "sources_sha": "bcab913dbf5b785a",
                     "valu_insts_per_cell_update": 5.3061,
                     "f64_insts_per_cell_update": 3.3631,
                     "f64_flops_per_cell_update": 4.8188},
