@@ -87,8 +87,12 @@ typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
  * modes produce the same integers.  LUT mode tabulates phi+ and phi- over the
  * initial state range [min q0, max q0], which bounds every later state by the
  * discrete maximum principle (Lemma cfl_monotone (i)); it is accepted for the
- * kinds for which that principle holds (UPWIND, BURGERS_EO).  The
- * temporally blocked kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
+ * kinds for which that principle holds (UPWIND, BURGERS_EO).  Building the
+ * table also checks that principle on the rounded maps themselves (phi+ never
+ * falls, phi- never rises and q - phi+ + phi- never falls from one state to the
+ * next); kernel 1 relies on it to read its slices without clamping, and takes
+ * the clamped reads for a table that fails the check.  The temporally blocked
+ * kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
  * from a per-tile slice in LDS when the tile's int32 states span fewer than
  * 512 levels (2048 for tiles of several wavefronts); their wider int32 tiles
  * and all their int64 tiles evaluate the maps the table was built from
