@@ -86,6 +86,18 @@ def test_levels_random_int64(lo, hi):
     _check_state(prob, q0)
 
 
+@pytest.mark.parametrize("lo,hi", [(-(1 << 20), 1 << 20), (-(1 << 40), 1 << 40)])
+def test_levels_random_int64_many_tiles(lo, hi):
+    # 73 sort tiles with a ragged last one; the second range takes the
+    # two-sort path for the transition pairs (their packed key needs 82 bits)
+    n = 300007
+    q0 = W.random_states(n, lo, hi, seed=72)
+    umax = max(abs(lo), abs(hi)) * 1e-6
+    prob = F.make_problem(F.FLUX_LF_LINEAR, 1e-6, 0.5 / max(umax, 1.0), n, itype=F.I64,
+                          a=0.5, alpha=1.0)
+    _check_state(prob, q0)
+
+
 def test_levels_constant_and_tiny():
     for n, val in [(1, 5), (2, -7), (64, 0), (1000, 123456)]:
         prob = F.make_problem(F.FLUX_UPWIND, 1e-3, 0.5, n, itype=F.I32)
