@@ -194,7 +194,7 @@ def bench_twin(F, W, plans, stream, int_value, reps=3):
                              "integer_table_over_fp64": int_value / rate}}
 
 
-def bench_batch(F, W, stream, G, reps=3):
+def bench_batch(F, W, stream, G, reps=5):
     """4096 instances (advection/Burgers, 256..65536 cells, 500..5000 steps) in
     one batched run against the one-instance-at-a-time loop on the same GPU;
     every instance's final state is checked against the oracle's digest."""
@@ -375,12 +375,19 @@ def _serve_run(F, items, arrivals, tick=64):
     assert all(c["status"] == 0 for c in comps)
     by_id = {c["id"]: c for c in comps}
     lat = np.array([by_id[i]["t_done"] - by_id[i]["t_submit"] for i in ids])
+    stats["service_s"] = np.array([by_id[i]["t_done"] - by_id[i]["t_admit"] for i in ids])
     return t1 - t0, lat, stats, outs
 
 
-def _pct(lat):
-    return {"p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99))}
+def _pct(lat, svc=None):
+    """p50/p99 of submit-to-done latency (queueing included) and, when given,
+    of admit-to-done service time."""
+    out = {"p50_latency_s": float(np.percentile(lat, 50)),
+           "p99_latency_s": float(np.percentile(lat, 99))}
+    if svc is not None:
+        out["p50_service_s"] = float(np.percentile(svc, 50))
+        out["p99_service_s"] = float(np.percentile(svc, 99))
+    return out
 
 
 def served_fp64_fields(cap):
@@ -454,9 +461,9 @@ def bench_serve(F, W, stream, G):
            "parity_vs_oracle": {"checked": checked, "bit_exact": ok}}
     rate = 0.7 * cap / (work / len(items))
     arr = W.poisson_arrivals(len(items), rate, seed=55)
-    t, lat, _, _ = _serve_run(F, items, arr)
+    t, lat, st7, _ = _serve_run(F, items, arr)
     res["load0.7"] = {"requests": "all", "arrival_rate_per_s": rate,
-                      "cell_updates_per_s": work / t, **_pct(lat)}
+                      "cell_updates_per_s": work / t, **_pct(lat, st7["service_s"])}
     log(f"[bench] W5 load 0.7: p50 {np.percentile(lat, 50):.3f}s p99 {np.percentile(lat, 99):.3f}s")
     rng = np.random.default_rng(77)
     sub = sorted(int(i) for i in rng.choice(len(items), size=min(SERVE_SUBSET, len(items)),
@@ -466,11 +473,12 @@ def bench_serve(F, W, stream, G):
     for load in (0.5, 0.9):
         rate = load * cap / (sub_work / len(sub))
         arr = W.poisson_arrivals(len(sub), rate, seed=55)
-        t, lat, _, _ = _serve_run(F, sub_items, arr)
+        t, lat, stl, _ = _serve_run(F, sub_items, arr)
         res[f"load{load}"] = {
             "requests": f"{len(sub)} drawn with numpy default_rng(77).choice "
                         f"({len(items)}, {len(sub)}, replace=False)",
-            "arrival_rate_per_s": rate, "cell_updates_per_s": sub_work / t, **_pct(lat)}
+            "arrival_rate_per_s": rate, "cell_updates_per_s": sub_work / t,
+            **_pct(lat, stl["service_s"])}
         log(f"[bench] W5 load {load} (subset): p50 {np.percentile(lat, 50):.3f}s "
             f"p99 {np.percentile(lat, 99):.3f}s")
     # FIFO: one request at a time through the single-grid stepper, against the
@@ -696,6 +704,23 @@ def cpu_baseline(W, level_state=None):
     res["w4_single_thread"] = {"value": sum(w.n * w.steps for w in ws) / d4, "cores": 1,
                                "seconds": d4,
                                "sample": "the first 32 of the 4096 instances, one after another"}
+    w1 = W.w1_advection_square()
+    r1c, d1c = scalar_rate(w1, w1.steps, False)
+    res["w1_single_thread"] = {"value": r1c, "cores": 1, "seconds": d1c,
+                               "sample": "the whole workload, 1024 cells x 1000 steps"}
+    # served Sod: the first 8 requests of the seeded set with at most 2^12
+    # cells, each solved in full (three components per cell-update)
+    reqs = [r for r in W.w5_sod_requests(count=SERVE_COUNT, nmax=SERVE_NMAX) if r.n <= 1 << 12][:8]
+    t0 = time.perf_counter()
+    for r in reqs:
+        op = O.Problem(O.EULER_ROE_EF, r.delta, r.lam, bc=O.OUTFLOW, gamma=r.gamma)
+        q = np.stack([O.quantise(r.U0[c], r.delta) for c in range(3)])
+        O.step_euler(op, q, r.steps, omp=True)
+    d5 = time.perf_counter() - t0
+    res["w5_all_cores"] = {"value": sum(r.n * r.steps for r in reqs) / d5, "cores": omp_threads,
+                           "seconds": d5,
+                           "sample": f"{len(reqs)} Sod requests of at most 2^12 cells (the first "
+                                     f"of the seeded set), each in full"}
     if level_state is not None:
         q = level_state
         t0 = time.perf_counter()
