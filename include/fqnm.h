@@ -140,7 +140,9 @@ typedef struct {
 /* Launch plan of the single-grid stepper.  kernel 0 = one step per pass
  * ("stream"); 1 = temporal blocking: every wavefront keeps a tile of 64*vec
  * consecutive cells in registers (vec consecutive cells per lane) and
- * advances it `depth` steps per pass over memory; 2 = temporal blocking with
+ * advances it `depth` steps per pass over memory (vec 4, 8 or 16 for int32
+ * states; 2, 4 or 8 for int64, and also 16 for int64 UPWIND maps evaluated
+ * directly, whose windows away from outflow ends step as exact doubles); 2 = temporal blocking with
  * lane-interleaved cells (consecutive cells in consecutive lanes, so table
  * reads coalesce), split kinds only; 3, 4, 5 = temporal blocking in
  * workgroup tiles of 2, 4 or 8 wavefronts; 6 = the d-D marching kernel: a
