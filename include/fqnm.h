@@ -91,7 +91,8 @@ typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
  * table also checks that principle on the rounded maps themselves (phi+ never
  * falls, phi- never rises and q - phi+ + phi- never falls from one state to the
  * next); kernel 1 relies on it to read its slices without clamping, and takes
- * the clamped reads for a table that fails the check.  The temporally blocked
+ * the clamped reads for a table that fails the check (or for every table when
+ * the environment variable FQNM_TABLE_CLAMPED is set at create).  The temporally blocked
  * kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
  * from a per-tile slice in LDS when the tile's int32 states span fewer than
  * 512 levels (2048 for tiles of several wavefronts); their wider int32 tiles

@@ -119,6 +119,28 @@ def test_kind_parity_all_plans(flux, a, lut, bc, itype):
         assert inv["sum"][0] == int(ref.sum())
 
 
+@pytest.mark.parametrize("flux,a", [(F.FLUX_BURGERS_EO, 1.0), (F.FLUX_UPWIND, 1.0),
+                                    (F.FLUX_UPWIND, -0.9)])
+@pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
+def test_table_clamped_and_certified_reads_agree(flux, a, bc, monkeypatch):
+    """Int32 tables certify the maximum principle at build, and kernel 1 then
+    reads its LDS slices without clamping; with FQNM_TABLE_CLAMPED set it
+    takes the clamped reads instead.  Both give the oracle's integers."""
+    n, steps = 20011, 130
+    u0, prob = make_case(flux, bc, F.I32, n, seed=211, a=a, lut=True)
+    op = oracle_problem(prob)
+    ref, led = O.step(op, O.quantise(u0, prob.delta, 32), steps, return_ledger=True)
+    for clamped in (False, True):
+        if clamped:
+            monkeypatch.setenv("FQNM_TABLE_CLAMPED", "1")
+        else:
+            monkeypatch.delenv("FQNM_TABLE_CLAMPED", raising=False)
+        for plan in ((F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 8, 64), (F.KERNEL_TBLOCK, 16, 96)):
+            q, inv = gpu_run(prob, u0=u0, steps=steps, plan=plan)
+            assert np.array_equal(q, ref), (clamped, plan)
+            assert inv["ledger"][0] == led
+
+
 @pytest.mark.parametrize("bc", [F.BC_PERIODIC, F.BC_OUTFLOW])
 @pytest.mark.parametrize("lo", [-192, -256])
 def test_table_tiles_at_the_slice_threshold(bc, lo):
