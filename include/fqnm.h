@@ -90,9 +90,12 @@ typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
  * kinds for which that principle holds (UPWIND, BURGERS_EO).  Building the
  * table also checks that principle on the rounded maps themselves (phi+ never
  * falls, phi- never rises and q - phi+ + phi- never falls from one state to the
- * next); kernel 1 relies on it to read its slices without clamping, and takes
- * the clamped reads for a table that fails the check (or for every table when
- * the environment variable FQNM_TABLE_CLAMPED is set at create).  The temporally blocked
+ * next); kernel 1 relies on it to step its LDS slices in the update's
+ * per-cell form g(q_i) + phi+(q_{i-1}) - phi-(q_{i+1}), g(q) = q - phi+(q) +
+ * phi-(q), from one unclamped read per cell, and takes the flux-difference
+ * form with clamped reads for a table that fails the check (or for every
+ * table when the environment variable FQNM_TABLE_CLAMPED is set at create):
+ * the integers are the same.  The temporally blocked
  * kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
  * from a per-tile slice in LDS when the tile's int32 states span fewer than
  * 512 levels (2048 for tiles of several wavefronts); their wider int32 tiles

@@ -350,35 +350,39 @@ __device__ __forceinline__ void tb_steps_upwind_f64(double c, int64_t (&q)[V], i
   for (int j = 0; j < V; ++j) q[j] = round_to<int64_t>(x[j]);
 }
 
-// The same step for a table that certifies the maximum principle (XParams
-// lut_mono): the window's first and last cells stay frozen, so every other
-// cell's update is the certified monotone function of three states of the
-// slice and stays in it, and no read needs a clamp.  The frozen cells are
-// halo; they take the place of the wrong values the zero-filled end moves
-// give the ends, and reach the stored interior no sooner.  keep_first and
-// keep_last are all-ones except in the wavefront's first and last lane
-// (zero there); masking the two end cells' flux differences with them costs
-// one instruction each, where the clamps cost one per cell.
+// One step in the update's per-cell form.  Regrouping the telescoping sum by
+// cell (Sec. 2.3), the new state is g(q_i) + phi+(q_{i-1}) - phi-(q_{i+1}) with
+// g(q) = q - phi+(q) + phi-(q), exactly in integers.  For a certified table
+// (XParams lut_mono) the wavefront's slice holds, for each state q of
+// [lo, lo + span], the pair
+//   x: the slice address of g(q) + phi+(lo) - phi-(lo),
+//   y: 8*(phi+(q) - phi+(lo)) in the low half, 8*(phi-(lo) - phi-(q)) in the
+//      high half,
+// both halves in [0, 8*span]: the certificate bounds each map's change
+// between consecutive states by one.  A step is one LDS read and two
+// instructions per cell, plus one cross-lane move for each of a lane's two
+// end cells.  The zero-filled moves make a missing neighbour at the window's
+// ends read as state lo; the
+// certified update is non-decreasing in each of its three states and fixes
+// constant states, so every state stays in [lo, lo + span] and no read
+// leaves the slice.  The ends' wrong values are halo and reach the stored
+// interior no sooner than the clamped step's.
 template <int V>
-__device__ __forceinline__ void tb_step_addr_frozen(uint32_t (&a)[V], uint32_t keep_first,
-                                                    uint32_t keep_last) {
-  uint32_t pp[V], pm[V];
+__device__ __forceinline__ void tb_step_addr3(uint32_t (&a)[V]) {
+  uint32_t G[V], O[V];
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     const uint64_t e = *(lds_u64*)(static_cast<uintptr_t>(a[j]));
-    pp[j] = static_cast<uint32_t>(e);
-    pm[j] = static_cast<uint32_t>(e >> 32);
+    G[j] = static_cast<uint32_t>(e);
+    O[j] = static_cast<uint32_t>(e >> 32);
   }
-  uint32_t F[V];
-#pragma unroll
-  for (int j = 0; j < V; ++j) F[j] = (j + 1 < V ? pm[j + 1] : tb_from_next_z(pm[0])) + pp[j];
-  const uint32_t Fl = tb_from_prev_z(F[V - 1]);
+  const uint32_t Ol = tb_from_prev_z(O[V - 1]), On = tb_from_next_z(O[0]);
 #pragma unroll
   for (int j = 0; j < V; ++j) {
-    uint32_t d = (j == 0 ? Fl : F[j - 1]) - F[j];
-    if (j == 0) d &= keep_first;
-    if (j == V - 1) d &= keep_last;
-    a[j] += d << 3;
+    const uint32_t left = j == 0 ? Ol : O[j - 1], right = j + 1 < V ? O[j + 1] : On;
+    // G + low half of left + high half of right: one bit-field insert and one
+    // sum of 16-bit halves, in place of two extractions and a 3-way add
+    a[j] = __builtin_amdgcn_sad_u16((left & 0xffffu) | (right & 0xffff0000u), 0u, G[j]);
   }
 }
 
@@ -446,19 +450,33 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
     const int64_t span = static_cast<int64_t>(mx) - mn;
     if (span < TB_WIN) {  // wavefront-uniform
       int2* w = s_win[wave];
-      for (int i = lane; i <= span; i += 64) {
-        const uint32_t off =
-            (static_cast<uint32_t>(mn) + static_cast<uint32_t>(i) - static_cast<uint32_t>(P.lut_lo))
-            << 3;
-        const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
-        w[i] = make_int2(e[0], e[1]);
+      const uint32_t base =
+          static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(w)));
+      const uint32_t off0 = (static_cast<uint32_t>(mn) - static_cast<uint32_t>(P.lut_lo)) << 3;
+      if (plain && P.lut_mono) {
+        // the per-cell form's entries (tb_step_addr3), relative to state mn
+        const auto e0 = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0, 0, 0);
+        const uint32_t p0 = static_cast<uint32_t>(e0[0]), m0 = static_cast<uint32_t>(e0[1]);
+        for (int i = lane; i <= span; i += 64) {
+          const auto e =
+              __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+          const uint32_t pp = static_cast<uint32_t>(e[0]), pm = static_cast<uint32_t>(e[1]);
+          // g(q) - mn + phi+(mn) - phi-(mn) with q = mn + i
+          const uint32_t gr = static_cast<uint32_t>(i) - (pp - p0) - (m0 - pm);
+          w[i] = make_int2(static_cast<int>(base + (gr << 3)),
+                           static_cast<int>(((pp - p0) << 3) | (((m0 - pm) << 3) << 16)));
+        }
+      } else {
+        for (int i = lane; i <= span; i += 64) {
+          const auto e =
+              __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+          w[i] = make_int2(e[0], e[1]);
+        }
       }
       // the slice written by some lanes is read by all lanes of this wavefront
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const uint32_t base =
-          static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(w)));
       const LdsWindow Wn{base - (static_cast<uint32_t>(mn) << 3),
                          base + (static_cast<uint32_t>(span) << 3)};
       if (plain) {
@@ -468,10 +486,7 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
         for (int j = 0; j < V; ++j)
           a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(mn)) << 3);
         if (P.lut_mono) {
-          // masks made by the zero-filling end moves, so that the compiler
-          // keeps them as masks rather than turning them into selects
-          const uint32_t keep_first = tb_from_prev_z(~0u), keep_last = tb_from_next_z(~0u);
-          for (int s = 0; s < ksteps; ++s) tb_step_addr_frozen<V>(a, keep_first, keep_last);
+          for (int s = 0; s < ksteps; ++s) tb_step_addr3<V>(a);
         } else {
           for (int s = 0; s < ksteps; ++s) tb_step_addr<V>(a, end);
         }
