@@ -260,7 +260,7 @@ fqnm_plan default_plan(const fqnm_problem& p, int pol) {
   fqnm_plan pl;
   pl.kernel = K_TBLOCK;
   pl.vec = p.itype == FQNM_I32 ? 4 : 8;
-  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 48 : 24;
+  pl.depth = p.itype == FQNM_I32 && p.eval == FQNM_EVAL_LUT ? 52 : 24;
   if (p.itype == FQNM_I64 && (pol == P_UPWIND_POS || pol == P_UPWIND_NEG)) {
     // 64-bit upwind windows step as exact doubles: wide tiles, deep passes
     pl.vec = 16;

@@ -685,11 +685,28 @@ __global__ __launch_bounds__(256) void k_persist(const int32_t* __restrict__ src
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          for (int i = lane; i < TB_WIN; i += 64) {
-            const uint32_t off = (static_cast<uint32_t>(lo) + static_cast<uint32_t>(i) -
-                                  static_cast<uint32_t>(P.lut_lo)) << 3;
-            const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
-            win[i] = make_int2(e[0], e[1]);
+          const uint32_t off0 = (static_cast<uint32_t>(lo) - static_cast<uint32_t>(P.lut_lo)) << 3;
+          if (P.lut_mono) {
+            // the per-cell form's entries (tb_step_addr3), relative to state
+            // lo; entries past the table's end are never reached
+            const uint32_t wbase =
+                static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_int2*)(win)));
+            const auto e0 = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0, 0, 0);
+            const uint32_t p0 = static_cast<uint32_t>(e0[0]), m0 = static_cast<uint32_t>(e0[1]);
+            for (int i = lane; i < TB_WIN; i += 64) {
+              const auto e = __builtin_amdgcn_raw_buffer_load_b64(
+                  L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+              const uint32_t pp = static_cast<uint32_t>(e[0]), pm = static_cast<uint32_t>(e[1]);
+              const uint32_t gr = static_cast<uint32_t>(i) - (pp - p0) - (m0 - pm);
+              win[i] = make_int2(static_cast<int>(wbase + (gr << 3)),
+                                 static_cast<int>(((pp - p0) << 3) | (((m0 - pm) << 3) << 16)));
+            }
+          } else {
+            for (int i = lane; i < TB_WIN; i += 64) {
+              const auto e = __builtin_amdgcn_raw_buffer_load_b64(
+                  L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+              win[i] = make_int2(e[0], e[1]);
+            }
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -703,7 +720,11 @@ __global__ __launch_bounds__(256) void k_persist(const int32_t* __restrict__ src
 #pragma unroll
         for (int j = 0; j < V; ++j)
           a[j] = base + ((static_cast<uint32_t>(q[j]) - static_cast<uint32_t>(slo)) << 3);
-        for (int s = 0; s < ks; ++s) tb_step_addr<V>(a, end);
+        if (P.lut_mono) {
+          for (int s = 0; s < ks; ++s) tb_step_addr3<V>(a);
+        } else {
+          for (int s = 0; s < ks; ++s) tb_step_addr<V>(a, end);
+        }
 #pragma unroll
         for (int j = 0; j < V; ++j)
           q[j] = static_cast<int32_t>(static_cast<uint32_t>(slo) +

@@ -135,7 +135,7 @@ def test_table_clamped_and_certified_reads_agree(flux, a, bc, monkeypatch):
             monkeypatch.setenv("FQNM_TABLE_CLAMPED", "1")
         else:
             monkeypatch.delenv("FQNM_TABLE_CLAMPED", raising=False)
-        for plan in ((F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 48), (F.KERNEL_TBLOCK, 8, 64),
+        for plan in ((F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 52), (F.KERNEL_TBLOCK, 8, 64),
                      (F.KERNEL_TBLOCK, 16, 96)):
             q, inv = gpu_run(prob, u0=u0, steps=steps, plan=plan)
             assert np.array_equal(q, ref), (clamped, plan)
@@ -166,7 +166,7 @@ def test_table_tiles_at_the_slice_threshold(bc, lo):
                           itype=F.I32, eval_=F.EVAL_LUT)
     op = oracle_problem(prob)
     ref, led = O.step(op, q0, 100, return_ledger=True)
-    plans = [None, (F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 48), (F.KERNEL_TBLOCK, 4, 8),
+    plans = [None, (F.KERNEL_TBLOCK, 4, 40), (F.KERNEL_TBLOCK, 4, 52), (F.KERNEL_TBLOCK, 4, 8),
              (F.KERNEL_TBLOCK, 8, 16), (F.KERNEL_TBLOCK, 16, 32)]
     if bc == F.BC_PERIODIC:
         plans += [(10, 4, 40), (10, 4, 8), (10, 8, 24)]
