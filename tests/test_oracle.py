@@ -155,6 +155,41 @@ def test_p4_max_principle_tvd_l1_order(kind, cfl):
     assert lo <= q.min() and q.max() <= hi
 
 
+CERT = [(O.BURGERS_EO, 1e-5, 0.45, 1.0), (O.BURGERS_EO, 1e-5, 1.0, 1.0),
+        (O.UPWIND, 1e-4, 0.9, 1.0), (O.UPWIND, 1e-4, 1.0, 1.0), (O.UPWIND, 1e-4, 0.9, -1.0),
+        (O.UPWIND, 1e-4, 1.0, -1.0), (O.UPWIND, 1e-4, 0.5, 0.7)]
+
+
+@pytest.mark.parametrize("kind,delta,cfl,a", CERT)
+def test_p4_rounded_split_maps_certify_the_maximum_principle(kind, delta, cfl, a):
+    """Lemma cfl_monotone on the rounded maps themselves: for CFL <= 1, from
+    one state to the next phi+ rises by 0 or 1, phi- falls by 0 or 1, never
+    both, so g(q) = q - phi+(q) + phi-(q) never falls.  Then the update
+    g(q_i) + phi+(q_{i-1}) - phi-(q_{i+1}) is non-decreasing in each state and
+    fixes constants, which is what lets the table path step without clamping.
+    The regrouped form equals the oracle's step on random grids."""
+    qmax = 30000
+    if kind == O.UPWIND:
+        p = O.Problem(kind, delta, cfl / abs(a), a=a)
+    else:
+        p = O.Problem(kind, delta, cfl / (delta * qmax))
+    qs = np.arange(-qmax, qmax + 1)
+    pp = np.array([O.phi(p, True, int(q)) for q in qs])
+    pm = np.array([O.phi(p, False, int(q)) for q in qs])
+    dp, dm = np.diff(pp), np.diff(pm)
+    assert set(np.unique(dp)) <= {0, 1} and set(np.unique(dm)) <= {-1, 0}
+    assert not np.any((dp != 0) & (dm != 0))
+    g = qs - pp + pm
+    assert np.all(np.diff(g) >= 0)
+    rng = np.random.default_rng(5)
+    for n in (3, 17, 256):
+        q = rng.integers(-qmax, qmax + 1, n)
+        i = q + qmax
+        H = g[i] + pp[np.roll(i, 1)] - pm[np.roll(i, -1)]
+        assert np.array_equal(O.step(p, q, 1), H)
+        assert H.min() >= q.min() and H.max() <= q.max()
+
+
 def test_p4_lf_counterexample_fixture():
     g = read_golden("lf_burgers_counterexample.txt")
     p = O.Problem(O.LF_BURGERS, float(g["delta"][0]), float(g["lambda"][0]),
