@@ -284,7 +284,8 @@ def test_interleaved_plan_rejected_for_two_point_kinds():
         F.fqnm_destroy(h)
 
 
-@pytest.mark.parametrize("bad", ["cfl", "lut_godunov", "range", "abi", "euler_i32", "n0"])
+@pytest.mark.parametrize("bad", ["cfl", "lut_godunov", "range", "lut_range", "abi", "euler_i32",
+                                 "n0"])
 def test_create_rejects_invalid_problems(bad):
     n = 100
     q0 = np.zeros(n, np.int32)
@@ -298,6 +299,10 @@ def test_create_rejects_invalid_problems(bad):
         prob.eval = F.EVAL_LUT
     elif bad == "range":
         q0 = np.full(n, 2 ** 31 - 10, np.int32)
+        want = F.ERR_RANGE
+    elif bad == "lut_range":  # a table over 2^28 or more states is refused before allocation
+        prob.eval = F.EVAL_LUT
+        q0[0], q0[1] = -(2 ** 27), 2 ** 27
         want = F.ERR_RANGE
     elif bad == "abi":
         prob.abi_version = 99
