@@ -1105,7 +1105,7 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     if (ctx->dim > 1) break;
     const int PER = i32 ? 4 : 2;
     if (v >= 2 * PER) cand.push_back({K_STREAM, v, 1, 0});
-    for (int d : {4, 8, 16, 32, 40, 48, 64, 96}) {
+    for (int d : {4, 8, 16, 32, 40, 48, 52, 56, 64, 96}) {
       const int kh = scalar_halo(K_TBLOCK, v, d);
       if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
     }
