@@ -270,6 +270,37 @@ fqnm_plan default_plan(const fqnm_problem& p, int pol) {
   return pl;
 }
 
+// SIMDs of a device (4 per compute unit), 0 if the runtime does not say.
+static int64_t device_simds(int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  return 4 * static_cast<int64_t>(cus > 0 ? cus : 0);
+}
+
+// A single grid small enough that a pass's wavefronts are about one per SIMD:
+// there the extra halo of a deeper pass costs no time, while every pass saved
+// saves a kernel boundary (about 3 us), so one solve of 1000 steps on 1024 to
+// 65536 cells takes half the time at 96-120 steps per pass as at 24.  Takes
+// the deepest pass of 4-cell lanes whose tiles number at most 1.75 per SIMD,
+// when it is deeper than the default plan's.
+static void small_grid_plan(const fqnm_problem& p, int device, fqnm_plan* pl) {
+  if (pl->vec == 16) return;  // 64-bit upwind: wide exact-double windows
+  const int64_t simds = device_simds(device);
+  if (simds <= 0) return;
+  for (int d : {120, 96, 80, 64, 52}) {
+    if (d <= pl->depth) break;
+    const int64_t T = 64 * 4 - 2 * static_cast<int64_t>(scalar_halo(K_TBLOCK, 4, d));
+    const int64_t tiles = (p.n + T - 1) / T;
+    if (4 * tiles <= 7 * simds) {
+      pl->kernel = K_TBLOCK;
+      pl->vec = 4;
+      pl->depth = d;
+      return;
+    }
+  }
+}
+
 }  // namespace fqnm
 
 using namespace fqnm;
@@ -468,7 +499,10 @@ static fqnm_status ctx_finish(fqnm_ctx* ctx) {
   ctx->pol = policy_of(p, lut);
   ctx->direct_pol = policy_of(p, false);
   fqnm_plan pl;
-  if (!lookup_plan(plan_key(p, ctx->pol), &pl)) pl = default_plan(p, ctx->pol);
+  if (!lookup_plan(plan_key(p, ctx->pol), &pl)) {
+    pl = default_plan(p, ctx->pol);
+    small_grid_plan(p, ctx->device, &pl);
+  }
   ctx->plan = pl;
   ctx->plan.eval = lut ? FQNM_EVAL_LUT : FQNM_EVAL_DIRECT;
   return FQNM_OK;
@@ -1092,6 +1126,7 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
   std::vector<fqnm_plan> cand;
   const bool i32 = ctx->prob.itype == FQNM_I32;
   const std::vector<int> vecs32{4, 8, 16}, vecs64{2, 4, 8, 16};
+  const int64_t simds = device_simds(ctx->device);
   if (ctx->dim > 1) {
     for (int v : {2, 4, 8})
       if (nd_variant_available(ctx->prob.itype, ctx->pol, v))
@@ -1108,6 +1143,14 @@ fqnm_status fqnm_autotune(fqnm_ctx* ctx, int64_t steps_per_trial) {
     for (int d : {4, 8, 16, 32, 40, 48, 52, 56, 64, 96}) {
       const int kh = scalar_halo(K_TBLOCK, v, d);
       if (64 * v - 2 * kh >= 32 * v) cand.push_back({K_TBLOCK, v, d, 0});
+    }
+    // deeper passes with small tiles, for grids of about one wavefront per
+    // SIMD (small_grid_plan)
+    for (int d : {80, 96, 120, 160, 200, 240, 320, 400, 480}) {
+      const int kh = scalar_halo(K_TBLOCK, v, d);
+      const int64_t T = 64 * v - 2 * kh;
+      if (T >= 8 && T < 32 * v && (ctx->prob.n + T - 1) / T <= 2 * simds)
+        cand.push_back({K_TBLOCK, v, d, 0});
     }
     for (int kb : {K_TBLOCK_B2, K_TBLOCK_B4, K_TBLOCK_B8}) {
       for (int d : {24, 48, 64, 96}) {

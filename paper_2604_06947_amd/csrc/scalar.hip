@@ -219,11 +219,14 @@ __global__ __launch_bounds__(256) void k_stream(const IT* __restrict__ src, IT* 
 // Interface fluxes of one step for the cells q[0..V) of every lane; the last
 // interface of a lane needs the next lane's first cell, the first cell's left
 // interface arrives from the previous lane.  With `edge` the outflow rules of
-// the domain ends apply at global positions g0+j (frozen outside [0, n)).
+// the domain ends apply at global positions g0+j (frozen outside [0, n)), and
+// the transfers across the two ends go to the ledger from the tiles that hold
+// cell 0 (own_left) and cell n-1 (own_right) only: a pass deeper than a tile
+// is wide reaches an end from several windows.
 template <typename IT, int POL, int V, bool EDGE, bool WIN = false>
 __device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, const LdsWindow& Wn,
-                                        IT (&q)[V], int64_t g0, int64_t n, bool own_right,
-                                        long long& led) {
+                                        IT (&q)[V], int64_t g0, int64_t n, bool own_left,
+                                        bool own_right, long long& led) {
   IT F[V];
   if constexpr (IsSplit<POL>::value) {
     IT pp[V], pm[V];
@@ -244,7 +247,7 @@ __device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, cons
         if (g == -1) f = ppR + pmR;        // F_{-1/2} = T(q_0, q_0)
         if (g == n - 1) f = pp[j] + pm[j]; // F_{n-1/2} = T(q_{n-1}, q_{n-1})
         F[j] = f;
-        if (g == -1) led += static_cast<long long>(f);
+        if (g == -1 && own_left) led += static_cast<long long>(f);
         if (g == n - 1 && own_right) led -= static_cast<long long>(f);
       }
     }
@@ -259,7 +262,7 @@ __device__ __forceinline__ void tb_step(const XParams& P, const LutView& L, cons
         if (g == -1) qL = qR;
         if (g == n - 1) qR = qL;
         F[j] = transfer<IT, POL>(P, qL, qR);
-        if (g == -1) led += static_cast<long long>(F[j]);
+        if (g == -1 && own_left) led += static_cast<long long>(F[j]);
         if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
       } else {
         F[j] = transfer<IT, POL>(P, qL, qR);
@@ -389,8 +392,8 @@ __device__ __forceinline__ void tb_step_addr3(uint32_t (&a)[V]) {
 // ksteps steps of a wavefront window with no LDS table slice.
 template <typename IT, int POL, int V>
 __device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView& L, IT (&q)[V],
-                                                int64_t g0, int64_t n, bool plain, bool own_right,
-                                                int ksteps, long long& led) {
+                                                int64_t g0, int64_t n, bool plain, bool own_left,
+                                                bool own_right, int ksteps, long long& led) {
   const LdsWindow Wn{0u, 0u};
   if constexpr (sizeof(IT) == 8 && (POL == P_UPWIND_POS || POL == P_UPWIND_NEG)) {
     if (plain) {
@@ -399,9 +402,11 @@ __device__ __forceinline__ void tb_steps_direct(const XParams& P, const LutView&
     }
   }
   if (plain) {
-    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, led);
+    for (int s = 0; s < ksteps; ++s)
+      tb_step<IT, POL, V, false>(P, L, Wn, q, g0, n, false, false, led);
   } else {
-    for (int s = 0; s < ksteps; ++s) tb_step<IT, POL, V, true>(P, L, Wn, q, g0, n, own_right, led);
+    for (int s = 0; s < ksteps; ++s)
+      tb_step<IT, POL, V, true>(P, L, Wn, q, g0, n, own_left, own_right, led);
   }
 }
 
@@ -428,6 +433,9 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
   long long led = 0;
   const LutView L = lut_view(P);
   const bool plain = inside || bc == FQNM_BC_PERIODIC;
+  // the tiles holding cells 0 and n-1 count the boundary transfers (with
+  // passes deeper than a tile is wide, other windows reach past the ends too)
+  const bool own_left = tstart == 0;
   const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
   bool done = false;
   if constexpr (POL == P_LUT && sizeof(IT) == 4) {
@@ -496,7 +504,7 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
                                  static_cast<uint32_t>(static_cast<int32_t>(a[j] - base) >> 3));
       } else {
         for (int s = 0; s < ksteps; ++s)
-          tb_step<IT, POL, V, true, true>(P, L, Wn, q, g0, n, own_right, led);
+          tb_step<IT, POL, V, true, true>(P, L, Wn, q, g0, n, own_left, own_right, led);
       }
       done = true;
     }
@@ -509,17 +517,20 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
       // step.
       switch (P.lut_pol) {
         case P_UPWIND_POS:
-          tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
+                                          led);
           break;
         case P_UPWIND_NEG:
-          tb_steps_direct<IT, P_UPWIND_NEG, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          tb_steps_direct<IT, P_UPWIND_NEG, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
+                                          led);
           break;
         default:
-          tb_steps_direct<IT, P_EO, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+          tb_steps_direct<IT, P_EO, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
+                                          led);
           break;
       }
     } else {
-      tb_steps_direct<IT, POL, V>(P, L, q, g0, n, plain, own_right, ksteps, led);
+      tb_steps_direct<IT, POL, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps, led);
     }
   }
   const int lane_lo = khalo / V, lane_hi = 64 - khalo / V;
@@ -736,17 +747,19 @@ __global__ __launch_bounds__(256) void k_persist(const int32_t* __restrict__ src
       if constexpr (POL == P_LUT) {
         switch (P.lut_pol) {
           case P_UPWIND_POS:
-            tb_steps_direct<int32_t, P_UPWIND_POS, V>(P, L, q, w + off0, n, true, false, ks, led);
+            tb_steps_direct<int32_t, P_UPWIND_POS, V>(P, L, q, w + off0, n, true, false, false, ks,
+                                                      led);
             break;
           case P_UPWIND_NEG:
-            tb_steps_direct<int32_t, P_UPWIND_NEG, V>(P, L, q, w + off0, n, true, false, ks, led);
+            tb_steps_direct<int32_t, P_UPWIND_NEG, V>(P, L, q, w + off0, n, true, false, false, ks,
+                                                      led);
             break;
           default:
-            tb_steps_direct<int32_t, P_EO, V>(P, L, q, w + off0, n, true, false, ks, led);
+            tb_steps_direct<int32_t, P_EO, V>(P, L, q, w + off0, n, true, false, false, ks, led);
             break;
         }
       } else {
-        tb_steps_direct<int32_t, POL, V>(P, L, q, w + off0, n, true, false, ks, led);
+        tb_steps_direct<int32_t, POL, V>(P, L, q, w + off0, n, true, false, false, ks, led);
       }
     }
     done += ks;
@@ -936,7 +949,7 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_wg(const int32_t* __restrict
     auto run = [&](auto pol) {
       constexpr int PD = decltype(pol)::value;
       for (int s = 0; s < ksteps; ++s) {
-        tb_step<int32_t, PD, V, false>(P, L, Wn, q, g0, n, false, led);
+        tb_step<int32_t, PD, V, false>(P, L, Wn, q, g0, n, false, false, led);
         if ((s + 1) % WG_H == 0 && s + 1 < ksteps) refresh(q, ((s + 1) / WG_H) & 1);
       }
     };
@@ -990,8 +1003,8 @@ using lds_ptr = __attribute__((address_space(3))) IT*;
 template <typename IT, int POL, int V, int NW, bool EDGE, bool WIN>
 __device__ __forceinline__ void blk_step(const XParams& P, const LutView& L, const LdsWindow& Wn,
                                          IT (&q)[V], lds_ptr<IT> s_edge, int s, int wave,
-                                         int lane, int64_t g0, int64_t n, bool own_right,
-                                         long long& led) {
+                                         int lane, int64_t g0, int64_t n, bool own_left,
+                                         bool own_right, long long& led) {
   const int b = s & 1;
   if (lane == 0) s_edge[(b * 2 + 0) * NW + wave] = q[0];
   if (lane == 63) s_edge[(b * 2 + 1) * NW + wave] = q[V - 1];
@@ -1022,7 +1035,7 @@ __device__ __forceinline__ void blk_step(const XParams& P, const LutView& L, con
         const IT ppR = j + 1 < V ? pp[j + 1] : ppn;
         if (g == -1) f = ppR + pmR;         // F_{-1/2} = T(q_0, q_0)
         if (g == n - 1) f = pp[j] + pm[j];  // F_{n-1/2} = T(q_{n-1}, q_{n-1})
-        if (g == -1) led += static_cast<long long>(f);
+        if (g == -1 && own_left) led += static_cast<long long>(f);
         if (g == n - 1 && own_right) led -= static_cast<long long>(f);
       }
       F[j] = f;
@@ -1045,7 +1058,7 @@ __device__ __forceinline__ void blk_step(const XParams& P, const LutView& L, con
         if (g == -1) qL = qR;
         if (g == n - 1) qR = qL;
         F[j] = transfer<IT, POL>(P, qL, qR);
-        if (g == -1) led += static_cast<long long>(F[j]);
+        if (g == -1 && own_left) led += static_cast<long long>(F[j]);
         if (g == n - 1 && own_right) led -= static_cast<long long>(F[j]);
       } else {
         F[j] = transfer<IT, POL>(P, qL, qR);
@@ -1097,6 +1110,7 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
   long long led = 0;
   const LutView L = lut_view(P);
   const bool plain = inside || bc == FQNM_BC_PERIODIC;
+  const bool own_left = tstart == 0;
   const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
   bool done = false;
   if constexpr (POL == P_LUT && sizeof(IT) == 4) {
@@ -1139,11 +1153,11 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
       if (plain) {
         for (int s = 0; s < ksteps; ++s)
           blk_step<IT, POL, V, NW, false, true>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
-                                                led);
+                                                false, led);
       } else {
         for (int s = 0; s < ksteps; ++s)
           blk_step<IT, POL, V, NW, true, true>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
-                                               own_right, led);
+                                               own_left, own_right, led);
       }
       done = true;
     }
@@ -1155,11 +1169,11 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
       if (plain) {
         for (int s = 0; s < ksteps; ++s)
           blk_step<IT, PD, V, NW, false, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n, false,
-                                                led);
+                                                false, led);
       } else {
         for (int s = 0; s < ksteps; ++s)
           blk_step<IT, PD, V, NW, true, false>(P, L, Wn, q, s_edge, s, wave, lane, g0, n,
-                                               own_right, led);
+                                               own_left, own_right, led);
       }
     };
     if constexpr (POL == P_LUT) {
@@ -1203,7 +1217,8 @@ __global__ __launch_bounds__(NW * 64) void k_tblock_blk(const IT* __restrict__ s
 template <typename IT, int POL, int V, bool EDGE>
 __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (&q)[V], int lane,
                                         int a_next,
-                                        int a_prev, int64_t wstart, int64_t n, bool own_right,
+                                        int a_prev, int64_t wstart, int64_t n, bool own_left,
+                                        bool own_right,
                                         long long& led) {
   IT pp[V], pm[V], F[V];
 #pragma unroll
@@ -1231,7 +1246,7 @@ __device__ __forceinline__ void il_step(const XParams& P, const LutView& L, IT (
       if (g == -1) f = ppR + pmR;
       if (g == n - 1) f = pp[j] + pm[j];
       F[j] = f;
-      if (g == -1) led += static_cast<long long>(f);
+      if (g == -1 && own_left) led += static_cast<long long>(f);
       if (g == n - 1 && own_right) led -= static_cast<long long>(f);
     }
   }
@@ -1278,11 +1293,13 @@ __global__ __launch_bounds__(256) void k_tblock_il(const IT* __restrict__ src,
   long long led = 0;
   if (inside || bc == FQNM_BC_PERIODIC) {
     for (int s = 0; s < ksteps; ++s)
-      il_step<IT, POL, V, false>(P, L, q, lane, a_next, a_prev, wstart, n, false, led);
+      il_step<IT, POL, V, false>(P, L, q, lane, a_next, a_prev, wstart, n, false, false, led);
   } else {
+    const bool own_left = tstart == 0;
     const bool own_right = tstart <= n - 1 && n - 1 < tstart + T;
     for (int s = 0; s < ksteps; ++s)
-      il_step<IT, POL, V, true>(P, L, q, lane, a_next, a_prev, wstart, n, own_right, led);
+      il_step<IT, POL, V, true>(P, L, q, lane, a_next, a_prev, wstart, n, own_left, own_right,
+                                led);
   }
   const int jlo = khalo / 64, jhi = V - khalo / 64;
 #pragma unroll

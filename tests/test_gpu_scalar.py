@@ -254,6 +254,50 @@ def test_create_on_device_keeps_state_in_tensor():
     assert np.array_equal(got, O.step(oracle_problem(prob), q0, 45))
 
 
+@pytest.mark.parametrize("flux,lut,n,depth", [
+    (F.FLUX_UPWIND, False, 1024, 120), (F.FLUX_BURGERS_EO, True, 1024, 120),
+    (F.FLUX_UPWIND, False, 8192, 120), (F.FLUX_UPWIND, False, 65536, 96),
+    (F.FLUX_UPWIND, False, 262144, 52), (F.FLUX_UPWIND, False, 1 << 20, 24)])
+def test_small_grids_take_deep_passes(flux, lut, n, depth):
+    """The default plan of a single grid (no tuned plan cached): the deepest
+    pass of 4-cell lanes whose tiles number at most 1.75 per SIMD (1024 SIMDs
+    on MI355X), when deeper than the default; bit-exact against the oracle."""
+    u0, prob = make_case(flux, F.BC_PERIODIC, F.I32, n, seed=29, lut=lut)
+    h = F.fqnm_create_from_field(prob, u0)
+    try:
+        pl = F.fqnm_get_plan(h)
+        F.fqnm_step(h, 250)
+        q = F.fqnm_get_state(h, prob).astype(np.int64)
+    finally:
+        F.fqnm_destroy(h)
+    assert (pl["kernel"], pl["vec"], pl["depth"]) == (F.KERNEL_TBLOCK, 4, depth)
+    assert np.array_equal(q, O.step(oracle_problem(prob), O.quantise(u0, prob.delta, 32), 250))
+
+
+@pytest.mark.parametrize("n", [777, 2112])
+def test_passes_deeper_than_tiles_on_outflow_grids(n):
+    """Passes deeper than a tile is wide: the windows of several tiles reach
+    past each end of an outflow grid, and only the tiles holding cell 0 and
+    cell n-1 may count the transfers across the ends.  States and ledger
+    against the oracle for every lane-contiguous, workgroup and interleaved
+    kernel with tiles narrower than their halo."""
+    plans = [(F.KERNEL_TBLOCK, 4, 120), (F.KERNEL_TBLOCK, 8, 240),
+             (F.KERNEL_TBLOCK_B4, 4, 400), (F.KERNEL_TBLOCK_IL, 8, 192)]
+    for flux, a, lut in [(F.FLUX_UPWIND, 1.0, False), (F.FLUX_UPWIND, -0.9, True),
+                         (F.FLUX_BURGERS_EO, 1.0, True), (F.FLUX_BURGERS_EO, 1.0, False),
+                         (F.FLUX_BURGERS_GODUNOV, 1.0, False)]:
+        u0, prob = make_case(flux, F.BC_OUTFLOW, F.I32, n, seed=41, a=a, lut=lut)
+        op = oracle_problem(prob)
+        q0 = O.quantise(u0, prob.delta, 32)
+        ref, led = O.step(op, q0, 300, return_ledger=True)
+        for plan in plans:
+            if plan[0] == F.KERNEL_TBLOCK_IL and flux in TWO_POINT:
+                continue
+            q, inv = gpu_run(prob, q0=q0.astype(np.int32), steps=300, plan=plan)
+            assert np.array_equal(q, ref), (flux, lut, plan)
+            assert inv["ledger"][0] == led, (flux, lut, plan)
+
+
 def test_autotune_then_parity():
     w = W.w2_burgers_step(n=1 << 16, steps=300)
     prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
