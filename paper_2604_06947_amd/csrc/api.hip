@@ -281,21 +281,25 @@ static int64_t device_simds(int device) {
 // A single grid small enough that a pass's wavefronts are about one per SIMD:
 // there the extra halo of a deeper pass costs no time, while every pass saved
 // saves a kernel boundary (about 3 us), so one solve of 1000 steps on 1024 to
-// 65536 cells takes half the time at 96-120 steps per pass as at 24.  Takes
-// the deepest pass of 4-cell lanes whose tiles number at most 1.75 per SIMD,
-// when it is deeper than the default plan's.
+// 65536 cells takes half the time at 96-120 steps per pass as at 24 (a third,
+// for 64-bit upwind states, of the time of their wide default windows).  Takes
+// the first plan of the list below whose tiles number at most 1.75 per SIMD
+// and whose pass is deeper than the default plan's: 4-cell lanes from 120
+// steps per pass down to 52, then, for 64-bit upwind states, exact-double
+// windows of 16-cell lanes at 200 steps.
 static void small_grid_plan(const fqnm_problem& p, int device, fqnm_plan* pl) {
-  if (pl->vec == 16) return;  // 64-bit upwind: wide exact-double windows
   const int64_t simds = device_simds(device);
   if (simds <= 0) return;
-  for (int d : {120, 96, 80, 64, 52}) {
-    if (d <= pl->depth) break;
-    const int64_t T = 64 * 4 - 2 * static_cast<int64_t>(scalar_halo(K_TBLOCK, 4, d));
+  const bool wide = pl->vec == 16;  // the default of 64-bit upwind states
+  static const int cands[][2] = {{4, 120}, {4, 96}, {4, 80}, {4, 64}, {4, 52}, {16, 200}};
+  for (const auto& c : cands) {
+    if ((c[0] == 16 && !wide) || c[1] <= pl->depth) continue;
+    const int64_t T = 64 * c[0] - 2 * static_cast<int64_t>(scalar_halo(K_TBLOCK, c[0], c[1]));
     const int64_t tiles = (p.n + T - 1) / T;
     if (4 * tiles <= 7 * simds) {
       pl->kernel = K_TBLOCK;
-      pl->vec = 4;
-      pl->depth = d;
+      pl->vec = c[0];
+      pl->depth = c[1];
       return;
     }
   }

@@ -254,15 +254,21 @@ def test_create_on_device_keeps_state_in_tensor():
     assert np.array_equal(got, O.step(oracle_problem(prob), q0, 45))
 
 
-@pytest.mark.parametrize("flux,lut,n,depth", [
-    (F.FLUX_UPWIND, False, 1024, 120), (F.FLUX_BURGERS_EO, True, 1024, 120),
-    (F.FLUX_UPWIND, False, 8192, 120), (F.FLUX_UPWIND, False, 65536, 96),
-    (F.FLUX_UPWIND, False, 262144, 52), (F.FLUX_UPWIND, False, 1 << 20, 24)])
-def test_small_grids_take_deep_passes(flux, lut, n, depth):
-    """The default plan of a single grid (no tuned plan cached): the deepest
-    pass of 4-cell lanes whose tiles number at most 1.75 per SIMD (1024 SIMDs
-    on MI355X), when deeper than the default; bit-exact against the oracle."""
-    u0, prob = make_case(flux, F.BC_PERIODIC, F.I32, n, seed=29, lut=lut)
+@pytest.mark.parametrize("flux,itype,lut,n,vec,depth", [
+    (F.FLUX_UPWIND, F.I32, False, 1024, 4, 120), (F.FLUX_BURGERS_EO, F.I32, True, 1024, 4, 120),
+    (F.FLUX_UPWIND, F.I32, False, 8192, 4, 120), (F.FLUX_UPWIND, F.I32, False, 65536, 4, 96),
+    (F.FLUX_UPWIND, F.I32, False, 262144, 4, 52), (F.FLUX_UPWIND, F.I32, False, 1 << 20, 4, 24),
+    (F.FLUX_UPWIND, F.I64, False, 1024, 4, 120), (F.FLUX_UPWIND, F.I64, False, 262144, 4, 52),
+    (F.FLUX_UPWIND, F.I64, False, 1 << 20, 16, 200),
+    (F.FLUX_BURGERS_EO, F.I64, False, 65536, 4, 96)])
+def test_small_grids_take_deep_passes(flux, itype, lut, n, vec, depth):
+    """The default plan of a single grid (no tuned plan cached): the first of
+    4-cell lanes at 120..52 steps per pass (then, for 64-bit upwind states,
+    16-cell lanes at 200) whose tiles number at most 1.75 per SIMD (1024 SIMDs
+    on MI355X) and whose pass is deeper than the default; bit-exact against
+    the oracle."""
+    u0, prob = make_case(flux, F.BC_PERIODIC, itype, n, seed=29, lut=lut)
+    width = 32 if itype == F.I32 else 64
     h = F.fqnm_create_from_field(prob, u0)
     try:
         pl = F.fqnm_get_plan(h)
@@ -270,8 +276,9 @@ def test_small_grids_take_deep_passes(flux, lut, n, depth):
         q = F.fqnm_get_state(h, prob).astype(np.int64)
     finally:
         F.fqnm_destroy(h)
-    assert (pl["kernel"], pl["vec"], pl["depth"]) == (F.KERNEL_TBLOCK, 4, depth)
-    assert np.array_equal(q, O.step(oracle_problem(prob), O.quantise(u0, prob.delta, 32), 250))
+    assert (pl["kernel"], pl["vec"], pl["depth"]) == (F.KERNEL_TBLOCK, vec, depth)
+    ref = O.step(oracle_problem(prob), O.quantise(u0, prob.delta, width), 250)
+    assert np.array_equal(q, ref)
 
 
 @pytest.mark.parametrize("n", [777, 2112])
