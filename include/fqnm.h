@@ -168,7 +168,14 @@ typedef struct {
  * launch can be resident at once (fqnm_set_plan checks).  d-D contexts run
  * kernels 6 and 9 only.  Zero fields mean "keep" (on a change between
  * kernels 6 and 9: that kernel's default, vec 4 (int64: 2) and 16 rows, or
- * vec 2 and 4 steps per pass). */
+ * vec 2 and 4 steps per pass).  A new 1-D context starts with the plan the
+ * autotuner cached for its shape, else kernel 1 with vec 4 (int32) or 8
+ * (int64), 52 steps per pass for int32 tables and 24 otherwise (int64 UPWIND:
+ * vec 16, 48 steps); a grid small enough that a deeper pass keeps about one
+ * wavefront per SIMD (at most 1.75 tiles per SIMD) takes instead the deepest
+ * such pass of 4-cell lanes, up to 120 steps (int64 UPWIND also 16-cell lanes
+ * at 200 steps), since there a pass costs about its launch whatever its
+ * halo. */
 typedef struct {
   int32_t kernel;
   int32_t vec;          /* cells per lane                                                */
