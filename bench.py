@@ -923,8 +923,13 @@ def main():
         w1 = W.w1_advection_square()
         p1 = F.make_problem(F.FLUX_UPWIND, w1.delta, w1.lam, w1.n, itype=F.I32, a=w1.a)
         t1, q1 = time_plain(F, p1, w1.u0, None, w1.steps, stream, reps=5)
+        h1 = F.fqnm_create_from_field(p1, w1.u0, stream)
+        pl1 = F.fqnm_get_plan(h1)  # the library's own choice for this grid
+        F.fqnm_destroy(h1)
         extras["w1_latency"] = {"cells": w1.n, "time_steps": w1.steps, "us_per_solve": t1 * 1e6,
                                 "cell_updates_per_s": w1.n * w1.steps / t1,
+                                "plan": {"kernel": pl1["kernel"], "vec": pl1["vec"],
+                                         "depth": pl1["depth"]},
                                 "parity_vs_oracle": parity("w1", q1, G)}
         log(f"[bench] W1 {t1*1e6:.1f} us per solve")
         # ---------------- the headline workload at one step per pass ---------------
