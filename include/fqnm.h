@@ -90,13 +90,13 @@ typedef enum { FQNM_I32 = 0, FQNM_I64 = 1 } fqnm_itype;
  * kinds for which that principle holds (UPWIND, BURGERS_EO).  Building the
  * table also checks that principle on the rounded maps themselves (phi+ never
  * falls, phi- never rises and q - phi+ + phi- never falls from one state to the
- * next); kernel 1 relies on it to step its LDS slices in the update's
+ * next); kernels 1 and 10 rely on it to step their LDS slices in the update's
  * per-cell form g(q_i) + phi+(q_{i-1}) - phi-(q_{i+1}), g(q) = q - phi+(q) +
- * phi-(q), from one unclamped read per cell, and takes the flux-difference
+ * phi-(q), from one unclamped read per cell, and take the flux-difference
  * form with clamped reads for a table that fails the check (or for every
  * table when the environment variable FQNM_TABLE_CLAMPED is set at create):
  * the integers are the same.  The temporally blocked
- * kernels (plan kernels 1, 3, 4, 5, 7 and 8) read the table
+ * kernels (plan kernels 1, 3, 4, 5, 7, 8 and 10) read the table
  * from a per-tile slice in LDS when the tile's int32 states span fewer than
  * 512 levels (2048 for tiles of several wavefronts); their wider int32 tiles
  * and all their int64 tiles evaluate the maps the table was built from
