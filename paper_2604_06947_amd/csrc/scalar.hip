@@ -365,11 +365,10 @@ __device__ __forceinline__ void tb_steps_upwind_f64(double c, int64_t (&q)[V], i
 // between consecutive states by one.  A step is one LDS read and two
 // instructions per cell, plus one cross-lane move for each of a lane's two
 // end cells.  The zero-filled moves make a missing neighbour at the window's
-// ends read as state lo; the
-// certified update is non-decreasing in each of its three states and fixes
-// constant states, so every state stays in [lo, lo + span] and no read
-// leaves the slice.  The ends' wrong values are halo and reach the stored
-// interior no sooner than the clamped step's.
+// ends read as state lo; the certified update is non-decreasing in each of
+// its three states and fixes constant states, so every state stays in
+// [lo, lo + span] and no read leaves the slice.  The ends' wrong values are
+// halo and reach the stored interior no sooner than the clamped step's.
 template <int V>
 __device__ __forceinline__ void tb_step_addr3(uint32_t (&a)[V]) {
   uint32_t G[V], O[V];
@@ -466,8 +465,8 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
         const auto e0 = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0, 0, 0);
         const uint32_t p0 = static_cast<uint32_t>(e0[0]), m0 = static_cast<uint32_t>(e0[1]);
         for (int i = lane; i <= span; i += 64) {
-          const auto e =
-              __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+          const uint32_t off = off0 + (static_cast<uint32_t>(i) << 3);
+          const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
           const uint32_t pp = static_cast<uint32_t>(e[0]), pm = static_cast<uint32_t>(e[1]);
           // g(q) - mn + phi+(mn) - phi-(mn) with q = mn + i
           const uint32_t gr = static_cast<uint32_t>(i) - (pp - p0) - (m0 - pm);
@@ -476,8 +475,8 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
         }
       } else {
         for (int i = lane; i <= span; i += 64) {
-          const auto e =
-              __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off0 + (static_cast<uint32_t>(i) << 3), 0, 0);
+          const uint32_t off = off0 + (static_cast<uint32_t>(i) << 3);
+          const auto e = __builtin_amdgcn_raw_buffer_load_b64(L.rsrc, off, 0, 0);
           w[i] = make_int2(e[0], e[1]);
         }
       }
@@ -517,16 +516,16 @@ __device__ __forceinline__ void tblock_tile(const IT* __restrict__ src, IT* __re
       // step.
       switch (P.lut_pol) {
         case P_UPWIND_POS:
-          tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
-                                          led);
+          tb_steps_direct<IT, P_UPWIND_POS, V>(P, L, q, g0, n, plain, own_left, own_right,
+                                               ksteps, led);
           break;
         case P_UPWIND_NEG:
-          tb_steps_direct<IT, P_UPWIND_NEG, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
-                                          led);
+          tb_steps_direct<IT, P_UPWIND_NEG, V>(P, L, q, g0, n, plain, own_left, own_right,
+                                               ksteps, led);
           break;
         default:
-          tb_steps_direct<IT, P_EO, V>(P, L, q, g0, n, plain, own_left, own_right, ksteps,
-                                          led);
+          tb_steps_direct<IT, P_EO, V>(P, L, q, g0, n, plain, own_left, own_right,
+                                       ksteps, led);
           break;
       }
     } else {
@@ -747,12 +746,12 @@ __global__ __launch_bounds__(256) void k_persist(const int32_t* __restrict__ src
       if constexpr (POL == P_LUT) {
         switch (P.lut_pol) {
           case P_UPWIND_POS:
-            tb_steps_direct<int32_t, P_UPWIND_POS, V>(P, L, q, w + off0, n, true, false, false, ks,
-                                                      led);
+            tb_steps_direct<int32_t, P_UPWIND_POS, V>(P, L, q, w + off0, n, true, false, false,
+                                                      ks, led);
             break;
           case P_UPWIND_NEG:
-            tb_steps_direct<int32_t, P_UPWIND_NEG, V>(P, L, q, w + off0, n, true, false, false, ks,
-                                                      led);
+            tb_steps_direct<int32_t, P_UPWIND_NEG, V>(P, L, q, w + off0, n, true, false, false,
+                                                      ks, led);
             break;
           default:
             tb_steps_direct<int32_t, P_EO, V>(P, L, q, w + off0, n, true, false, false, ks, led);
