@@ -305,6 +305,29 @@ def test_passes_deeper_than_tiles_on_outflow_grids(n):
             assert inv["ledger"][0] == led, (flux, lut, plan)
 
 
+def test_autotune_small_grid_considers_deep_passes():
+    """On a grid of one or two tiles per SIMD the autotuner also times passes
+    deeper than a tile is wide (up to 120 steps in 4-cell lanes): the plan it
+    keeps is a blocked one at least 52 steps deep, and steps the grid (outflow
+    ends, so the ledger too) bit-exactly."""
+    w = W.w1_advection_square()
+    prob = F.make_problem(F.FLUX_UPWIND, w.delta, w.lam, w.n, itype=F.I32, a=w.a,
+                          bc=F.BC_OUTFLOW)
+    h = F.fqnm_create_from_field(prob, w.u0)
+    try:
+        F.fqnm_autotune(h, 240)
+        plan = F.fqnm_get_plan(h)
+        F.fqnm_step(h, w.steps)
+        q = F.fqnm_get_state(h, prob).astype(np.int64)
+        inv = F.fqnm_invariants_get(h)
+    finally:
+        F.fqnm_destroy(h)
+    assert plan["kernel"] != F.KERNEL_STREAM and plan["depth"] >= 52, plan
+    ref, led = O.step(oracle_problem(prob), O.quantise(w.u0, w.delta, 32), w.steps,
+                      return_ledger=True)
+    assert np.array_equal(q, ref) and inv["ledger"][0] == led
+
+
 def test_autotune_then_parity():
     w = W.w2_burgers_step(n=1 << 16, steps=300)
     prob = F.make_problem(F.FLUX_BURGERS_EO, w.delta, w.lam, w.n, itype=F.I32,
