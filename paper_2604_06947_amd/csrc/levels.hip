@@ -313,6 +313,84 @@ __global__ void k_run_counts(const int32_t* __restrict__ rstart, int32_t* __rest
   GRID_STRIDE(r, m) cnt[r] = static_cast<int32_t>((r + 1 < m ? rstart[r + 1] : n) - rstart[r]);
 }
 
+// ---------------------------------------------------------------------------
+// Direct level histogram, for states spanning a moderate range [lo, hi]: a
+// block counts its HIST_CELLS cells in an LDS histogram over the block's own
+// range when that fits (states of neighbouring cells are close), then adds
+// its non-zero bins to the global histogram; otherwise it counts straight
+// into the global histogram.  The non-zero bins, in increasing level order,
+// are the levels; their bins the counts.
+// ---------------------------------------------------------------------------
+constexpr int HIST_T = 256, HIST_R = 16, HIST_CELLS = HIST_T * HIST_R, HIST_LDS = 8192;
+
+template <typename IT>
+__global__ __launch_bounds__(HIST_T) void k_hist(const IT* __restrict__ q, int64_t n, int64_t lo,
+                                                 int32_t* __restrict__ hist) {
+  __shared__ int32_t s_h[HIST_LDS];
+  __shared__ int64_t s_mn[HIST_T / 64], s_mx[HIST_T / 64];
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * HIST_CELLS;
+  const int64_t c1 = c0 + HIST_CELLS < n ? c0 + HIST_CELLS : n;
+  int64_t v[HIST_R];
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+#pragma unroll
+  for (int r = 0; r < HIST_R; ++r) {  // coalesced: consecutive threads, consecutive cells
+    const int64_t i = c0 + r * HIST_T + threadIdx.x;
+    v[r] = i < c1 ? static_cast<int64_t>(q[i]) - lo : -1;
+    if (i < c1) {
+      mn = v[r] < mn ? v[r] : mn;
+      mx = v[r] > mx ? v[r] : mx;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int64_t a = __shfl_xor(mn, off, 64), b = __shfl_xor(mx, off, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_mn[threadIdx.x >> 6] = mn;
+    s_mx[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  for (int w = 0; w < HIST_T / 64; ++w) {
+    mn = s_mn[w] < mn ? s_mn[w] : mn;
+    mx = s_mx[w] > mx ? s_mx[w] : mx;
+  }
+  if (mx - mn < HIST_LDS) {  // block-uniform
+    const int span = static_cast<int>(mx - mn) + 1;
+    for (int b = threadIdx.x; b < span; b += HIST_T) s_h[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < HIST_R; ++r)
+      if (v[r] >= 0) atomicAdd(&s_h[v[r] - mn], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < span; b += HIST_T)
+      if (s_h[b] != 0) atomicAdd(&hist[mn + b], s_h[b]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < HIST_R; ++r)
+      if (v[r] >= 0) atomicAdd(&hist[v[r]], 1);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n) { GRID_STRIDE(i, n) p[i] = 0; }
+
+__global__ void k_nonzero(const int32_t* __restrict__ h, int32_t* __restrict__ flag, int64_t n) {
+  GRID_STRIDE(i, n) flag[i] = h[i] != 0 ? 1 : 0;
+}
+
+// The non-zero bins in order: level lo + b and its count, at their rank.
+__global__ void k_bins_out(const int32_t* __restrict__ h, const int32_t* __restrict__ rank,
+                           int64_t lo, int64_t* __restrict__ lev, int32_t* __restrict__ cnt,
+                           int64_t n) {
+  GRID_STRIDE(b, n) {
+    if (h[b] != 0) {
+      lev[rank[b]] = lo + b;
+      cnt[rank[b]] = h[b];
+    }
+  }
+}
+
 // v[r] = N_{k'k} / c_k for run r = (k, k'); runs are sorted by k, so c_k is the
 // sum of the counts of k's block, read off the inclusive prefix sums P.
 __global__ void k_row_terms(const int64_t* __restrict__ rk, const int32_t* __restrict__ cnt,
@@ -419,6 +497,58 @@ fqnm_status levels_of(fqnm_ctx* ctx, std::vector<int64_t>& lv, std::vector<int64
   if (lo == hi) {
     lv.assign(1, lo);
     ct.assign(1, n);
+    return FQNM_OK;
+  }
+  // a range of at most max(4n, 2^16) levels (and 2^24): count them directly
+  const int64_t R = hi - lo + 1;
+  if (R <= (int64_t(1) << 24) && R <= std::max<int64_t>(4 * n, int64_t(1) << 16)) {
+    int32_t *hist = nullptr, *flag = nullptr, *rank = nullptr, *cnt = nullptr, *scan = nullptr;
+    int64_t* lev = nullptr;
+    auto hlayout = [&](char* base) {
+      Carver c{base};
+      hist = c.take<int32_t>(R);
+      flag = c.take<int32_t>(R);
+      rank = c.take<int32_t>(R);
+      cnt = c.take<int32_t>(R);
+      lev = c.take<int64_t>(R);
+      scan = c.take<int32_t>(scan_scratch(R));
+      return c.off;
+    };
+    char* hbase = nullptr;
+    st = workspace(ctx, hlayout(nullptr), &hbase);
+    if (st) return st;
+    hlayout(hbase);
+    k_fill_i32<<<grid_of(R), 256, 0, s>>>(hist, R);
+    LV_HIP(hipGetLastError(), "histogram reset");
+    const unsigned hb = static_cast<unsigned>((n + HIST_CELLS - 1) / HIST_CELLS);
+    if (ctx->prob.itype == FQNM_I32)
+      k_hist<int32_t><<<hb, HIST_T, 0, s>>>(static_cast<const int32_t*>(ctx->buf[ctx->cur]), n,
+                                             lo, hist);
+    else
+      k_hist<int64_t><<<hb, HIST_T, 0, s>>>(static_cast<const int64_t*>(ctx->buf[ctx->cur]), n,
+                                             lo, hist);
+    LV_HIP(hipGetLastError(), "histogram");
+    k_nonzero<<<grid_of(R), 256, 0, s>>>(hist, flag, R);
+    LV_HIP(hipGetLastError(), "occupied bins");
+    LV_HIP(scan_i32(flag, rank, R, false, scan, s), "scan");
+    k_bins_out<<<grid_of(R), 256, 0, s>>>(hist, rank, lo, lev, cnt, R);
+    LV_HIP(hipGetLastError(), "levels");
+    int32_t last_rank = 0, last_flag = 0;
+    LV_HIP(hipMemcpyAsync(&last_rank, rank + (R - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s),
+           "copy");
+    LV_HIP(hipMemcpyAsync(&last_flag, flag + (R - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s),
+           "copy");
+    LV_HIP(hipStreamSynchronize(s), "sync");
+    const int32_t m = last_rank + last_flag;
+    std::vector<int32_t> c32(m);
+    lv.resize(m);
+    LV_HIP(hipMemcpyAsync(lv.data(), lev, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s),
+           "copy levels");
+    LV_HIP(hipMemcpyAsync(c32.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s),
+           "copy counts");
+    LV_HIP(hipStreamSynchronize(s), "sync");
+    ct.resize(m);
+    for (int32_t j = 0; j < m; ++j) ct[j] = c32[j];
     return FQNM_OK;
   }
   const int bits = bit_length(static_cast<uint64_t>(hi - lo));

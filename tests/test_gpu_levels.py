@@ -86,9 +86,12 @@ def test_levels_random_int64(lo, hi):
     _check_state(prob, q0)
 
 
-@pytest.mark.parametrize("lo,hi", [(-(1 << 20), 1 << 20), (-(1 << 40), 1 << 40)])
+@pytest.mark.parametrize("lo,hi", [(-150000, 150000), (-(1 << 20), 1 << 20),
+                                   (-(1 << 40), 1 << 40)])
 def test_levels_random_int64_many_tiles(lo, hi):
-    # 73 sort tiles with a ragged last one; the second range takes the
+    # the first range is counted directly (at most 4n levels), each block
+    # spanning far more levels than its LDS histogram holds; the others take
+    # the sort: 73 tiles with a ragged last one, and for the widest range the
     # two-sort path for the transition pairs (their packed key needs 82 bits)
     n = 300007
     q0 = W.random_states(n, lo, hi, seed=72)
